@@ -1,0 +1,168 @@
+"""Synthetic workloads and seeded inputs shared by the tests and the benchmark.
+
+This module holds parameter values and random draws only; it contains none of
+the method's arithmetic (no z fit, no CPML profile, no Bessel value). Both the
+HIP solver and the CPU reference receive these plain numbers and derive
+everything else on their own.
+
+All configurations use λ = 800 nm, Courant number 0.5, E0 = 1, a sin² turn-on
+ramp, CPML with polynomial grade 3, σ_max equal to the usual optimum
+0.8 (g+1)/(η0 Δ), κ_max = 1 and a CFS pole α_max one tenth of the carrier
+frequency (normalised α Δx/(ε0 c) = 0.1 · 2π/n_s).
+
+The parameter sets follow the paper's workloads (§4, Table 1 and the sampling
+rule; §5): a y-polarised order-m Bessel beam from a thin annulus, z-periodic
+box of whole axial periods, CPML on x and y.
+"""
+import math
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+WAVELENGTH = 800e-9
+C_LIGHT = 299792458.0
+PERIOD = WAVELENGTH / C_LIGHT            # optical period, s
+
+BC_CPML, BC_PEC, BC_PERIODIC = 0, 1, 2
+RAMP_SIN2, RAMP_GAUSS, RAMP_CW = 0, 1, 2
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz_hint: int
+    ns: float                  # cells per wavelength (Δx = λ/ns)
+    theta_deg: float
+    order: int
+    r_outer_cells: float
+    thickness_cells: float
+    npml: int
+    steps: int
+    ramp_periods: float = 20.0
+    courant: float = 0.5
+    bc: int = BC_CPML
+    e0: float = 1.0
+    grade: float = 3.0
+    sigma_scale: float = 1.0
+    kappa_max: float = 1.0
+    window_periods: float = 5.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def dx(self):
+        return WAVELENGTH / self.ns
+
+    @property
+    def theta(self):
+        return math.radians(self.theta_deg)
+
+    @property
+    def alpha_max(self):
+        return 0.1 * 2.0 * math.pi / self.ns
+
+    @property
+    def ramp_seconds(self):
+        return self.ramp_periods * PERIOD
+
+    @property
+    def steps_per_period(self):
+        return self.ns / self.courant
+
+    @property
+    def window_steps(self):
+        return int(round(self.window_periods * self.steps_per_period))
+
+
+def config0():
+    """32×32×32, Δx = λ/16, θ = 10°, m = 0, annulus 12Δx × 2Δx, 8-cell CPML, 200 steps."""
+    return Workload("c0_32cube_theta10_m0", 32, 32, 32, 16.0, 10.0, 0, 12.0, 2.0, 8, 200)
+
+
+def config1(order=0):
+    """256×256×64 (z fitted), Δx = λ/20, θ = 15°, m = 0 or 1, annulus 100Δx, 2000 steps."""
+    return Workload(f"c1_256x256x64_theta15_m{order}", 256, 256, 64, 20.0, 15.0, order,
+                    100.0, 2.0, 16, 2000)
+
+
+def config2():
+    """768×768×256 (z fitted to 255), Δx = λ/24, θ = 20°, m = 2, annulus 320Δx, 1000 steps."""
+    return Workload("c2_768x768x256_theta20_m2", 768, 768, 256, 24.0, 20.0, 2, 320.0, 2.0,
+                    16, 1000)
+
+
+def config3_instances(seed=1, count=64):
+    """64 uneven instances: nx = ny ~ U{64..160}, nz_hint ~ U{48..64},
+    θ ~ {5,10,15,20,25,30}°, m ~ U{0..3}; 8-cell CPML, R_B = 0.8 (nx/2 - 8) Δx."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        nx = int(rng.integers(64, 161))
+        nzh = int(rng.integers(48, 65))
+        th = float(rng.choice([5.0, 10.0, 15.0, 20.0, 25.0, 30.0]))
+        m = int(rng.integers(0, 4))
+        out.append(Workload(f"c3_inst{q:02d}", nx, nx, nzh, 20.0, th, m,
+                            0.8 * (nx / 2 - 8), 2.0, 8, 1000))
+    return out
+
+
+def config4():
+    """192×192×64 (z fitted), Δx = λ/20, θ = 12°, m = 0, annulus 64Δx, 1500 steps,
+    checkpoints every 100 steps, 256 sector weights, 10-period ramp."""
+    return Workload("c4_192x192x64_theta12_m0", 192, 192, 64, 20.0, 12.0, 0, 64.0, 2.0,
+                    16, 1500, ramp_periods=10.0,
+                    extra={"checkpoint_every": 100, "sectors": 256})
+
+
+def config4_sector_params(seed=2, sectors=256):
+    """Initial sector amplitudes a = 1 + 0.05 N(0,1) and phases φ = 0.1 N(0,1)
+    (amplitudes drawn first)."""
+    rng = np.random.default_rng(seed)
+    amp = 1.0 + 0.05 * rng.standard_normal(sectors)
+    phase = 0.1 * rng.standard_normal(sectors)
+    return amp, phase
+
+
+def config4_fd_sectors():
+    """The 16 finite-difference probes: amplitude and phase of sectors 32q + 5."""
+    return [32 * q + 5 for q in range(8)]
+
+
+def validation_run(order=0, n_perp=2, ns=16.0):
+    """Paper-regime check (§4 Table 1 geometry scaled down): θ = 30°, n_s = 16
+    (the paper's 20 on request), R_B = n_perp λ_xy, δs = 1 λ, 12-cell CPML,
+    one axial period, 10-period ramp; the run lasts ramp + inward transit
+    R_B/(c sin θ) + 6 periods."""
+    th = 30.0
+    lam_xy = ns / math.sin(math.radians(th))
+    r_b = n_perp * lam_xy
+    npml = 12
+    n = int(2 * r_b) + 2 * npml
+    transit = r_b / math.sin(math.radians(th))          # Δx units of time
+    ramp_p = 10.0
+    steps = int(round((ramp_p * ns + transit) / 0.5 + 6 * ns / 0.5))
+    nz_hint = int(round(ns / math.cos(math.radians(th))))
+    return Workload(f"v_theta30_m{order}_nperp{n_perp}_ns{int(ns)}", n, n, nz_hint, ns, th,
+                    order, r_b, ns, npml, steps, ramp_periods=ramp_p)
+
+
+def random_fields(shape, seed=0):
+    """Six U(-1, 1) fields in the order Ex, Ey, Ez, Hx, Hy, Hz, each [nz, ny, nx]."""
+    rng = np.random.default_rng(seed)
+    return [rng.uniform(-1.0, 1.0, size=shape) for _ in range(6)]
+
+
+def random_state_vectors(shape_f, shapes_psi, seed):
+    """Random fields and CPML memories for transpose (dot-product) tests."""
+    rng = np.random.default_rng(seed)
+    f = [rng.standard_normal(shape_f) for _ in range(6)]
+    p = [rng.standard_normal(s) for s in shapes_psi]
+    return f, p
+
+
+def parity_small():
+    """Several-tile case with ragged edges: 100×72×(40 hint), source in the
+    interior, 16-cell CPML, θ = 18°, m = 1, 60 steps."""
+    return Workload("p_100x72x40_theta18_m1", 100, 72, 40, 14.0, 18.0, 1, 26.0, 3.0,
+                    10, 60, ramp_periods=2.0)
