@@ -1,0 +1,228 @@
+/*
+ * besselfdtd — MI355X (gfx950) FDTD solver for the Bessel-antenna method of
+ * Ardaneh, Giust, Morel and Courvoisier, "Generation of a Bessel beam in FDTD
+ * using a cylindrical antenna" (Opt. Express; arXiv 2102.12978).
+ *
+ * C ABI. Plain pointers and sizes only. Unless a call says otherwise:
+ *   - host pointers are read (or written) during the call only, never kept;
+ *   - the library owns every context and every device buffer it allocates;
+ *   - a context is used by one host thread at a time;
+ *   - fdtd_step and the adjoint/batch step calls are asynchronous on the
+ *     stream given at creation; every read-back synchronises that stream;
+ *   - no C++ exception or abort crosses the ABI: failures return a negative
+ *     code and fdtd_last_error(ctx) holds a message.
+ *
+ * Units. Inputs are SI (metres, seconds, radians). Internally lengths are in
+ * Δx, time in Δx/c, c = ε0 = μ0 = 1 and H is stored as H̃ = η0 H. Field
+ * arrays on the host side are float32, indexed [k][j][i] = [z][y][x]
+ * (x fastest), component order Ex, Ey, Ez, Hx, Hy, Hz.
+ *
+ * Discretisation (paper §4): standard second-order Yee scheme; E_x at
+ * (i+½, j, k), E_y (i, j+½, k), E_z (i, j, k+½), H_x (i, j+½, k+½),
+ * H_y (i+½, j, k+½), H_z (i+½, j+½, k). One step takes (E^n, H̃^{n+½}) to
+ * (E^{n+1}, H̃^{n+3/2}): E update, then the E soft source at t_{n+1}, then the
+ * H update, then the H soft source at t_{n+3/2}. z is periodic; x and y end
+ * on PEC walls backed by a convolutional PML (CPML, §4), or are periodic in
+ * the test mode FDTD_BC_PERIODIC.
+ */
+#ifndef BESSELFDTD_FDTD_H
+#define BESSELFDTD_FDTD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define FDTD_OK         0
+#define FDTD_EINVAL    (-1)   /* bad argument (nothing was changed)          */
+#define FDTD_ENOMEM    (-2)   /* device or host allocation failed            */
+#define FDTD_EDEVICE   (-3)   /* a HIP call failed (no GPU, launch error)    */
+#define FDTD_ESTATE    (-4)   /* call out of order (e.g. no injector set)   */
+#define FDTD_EUNSTABLE (-5)   /* NaN/Inf or energy blow-up detected          */
+
+/* ---- transverse boundary (x and y) ------------------------------------- */
+#define FDTD_BC_CPML     0    /* CPML of cpml_cells cells, PEC behind it      */
+#define FDTD_BC_PEC      1    /* bare PEC walls (cpml_cells must be 0)        */
+#define FDTD_BC_PERIODIC 2    /* x and y periodic (test mode, no CPML)        */
+
+/* ---- temporal envelope f(t) of the injected fields (§4) ---------------- */
+#define FDTD_RAMP_SIN2  0     /* f = sin²(π t / 2 T_r) for t < T_r, then 1    */
+#define FDTD_RAMP_GAUSS 1     /* f = exp(-(t - T0)² / T²), phase e^{-iω(t-T0)}*/
+#define FDTD_RAMP_CW    2     /* f = 1                                        */
+
+/* ---- kernel choice ------------------------------------------------------ */
+#define FDTD_KERNEL_AUTO  0   /* fused kernel, tile shape from the autotuner  */
+#define FDTD_KERNEL_SPLIT 1   /* two kernels per step (E, then H)            */
+#define FDTD_KERNEL_FUSED 2   /* one fused E-then-H kernel per step           */
+
+/* ---- state arrays for fdtd_get_state / fdtd_set_state ------------------
+ * Fields: [nz][ny][nx]. CPML memories ψ live only in the slabs: the x-slab
+ * arrays (ψ of the x derivatives: EYX, EZX, HYX, HZX) are [nz][ny][2*cpml]
+ * holding x = 0..cpml-1 then x = nx-cpml..nx-1; the y-slab arrays (EXY, EZY,
+ * HXY, HZY) are [nz][2*cpml][nx] holding y = 0..cpml-1 then ny-cpml..ny-1.  */
+#define FDTD_EX 0
+#define FDTD_EY 1
+#define FDTD_EZ 2
+#define FDTD_HX 3
+#define FDTD_HY 4
+#define FDTD_HZ 5
+#define FDTD_PSI_EXY 6
+#define FDTD_PSI_EYX 7
+#define FDTD_PSI_EZX 8
+#define FDTD_PSI_EZY 9
+#define FDTD_PSI_HXY 10
+#define FDTD_PSI_HYX 11
+#define FDTD_PSI_HZX 12
+#define FDTD_PSI_HZY 13
+
+/* ---- diagnostics mask (fdtd_set_diagnostics) ---------------------------- */
+#define FDTD_DIAG_EX2    1u   /* accumulate E_x² on the plane                */
+#define FDTD_DIAG_EY2    2u   /* accumulate E_y² on the plane (§5 intensity) */
+#define FDTD_DIAG_EZ2    4u   /* accumulate E_z² on the plane                */
+#define FDTD_DIAG_ENERGY 8u   /* W^{n+1} = Σ(E^{n+1})² + Σ H̃^{n+½}·H̃^{n+3/2}  */
+
+typedef struct fdtd_ctx fdtd_ctx;
+
+typedef struct fdtd_grid {
+    int32_t nx, ny, nz;       /* cells; nx, ny >= 2, nz >= 1                  */
+    double dx, dy, dz;        /* cell sizes (m); dz normally from              */
+                              /* fdtd_fit_periodic_z                           */
+    double courant;           /* S = c Δt / Δx; S·sqrt(1+(Δx/Δy)²+(Δx/Δz)²)<1 */
+    int32_t bc_xy;            /* FDTD_BC_*                                     */
+    int32_t cpml_cells;       /* CPML thickness (cells), 1 <= cpml <= n/2      */
+    double cpml_grade;        /* polynomial grade g of σ and κ                 */
+    double cpml_sigma_scale;  /* σ_max in units of 0.8 (g+1) / (η0 Δ)          */
+    double cpml_kappa_max;    /* κ at the PEC wall (>= 1)                      */
+    double cpml_alpha_max;    /* CFS α at the interface, α Δx / (ε0 c)          */
+    int32_t kernel;           /* FDTD_KERNEL_*                                 */
+    int32_t reserved;         /* set to 0                                      */
+    void *stream;             /* hipStream_t to run on; NULL = null stream     */
+} fdtd_grid;
+
+typedef struct fdtd_injector {
+    double wavelength;        /* λ (m)                                         */
+    double theta;             /* cone angle θ (rad), 0 < θ < π/2               */
+    int32_t order;            /* Bessel order m >= 0 (the paper's m)           */
+    int32_t ramp_kind;        /* FDTD_RAMP_*                                   */
+    double e0;                /* amplitude E0 of the injected TE Π_x beam      */
+    double r_outer;           /* outer antenna radius R_B (m)                  */
+    double thickness;         /* antenna thickness δs (m), 0 < δs < R_B        */
+    double axis_x, axis_y;    /* beam axis from the x = 0 / y = 0 walls (m);   */
+                              /* NaN = grid centre                             */
+    double ramp_a;            /* SIN2: T_r (s); GAUSS: T (s)                   */
+    double ramp_b;            /* GAUSS: T0 (s)                                 */
+    int32_t n_sectors;        /* 0, or number of angular sectors of weights    */
+    int32_t reserved;         /* set to 0                                      */
+    const double *sector_amp;   /* host [n_sectors] amplitudes a_s, or NULL    */
+    const double *sector_phase; /* host [n_sectors] phases φ_s (rad), or NULL  */
+} fdtd_injector;
+
+typedef struct fdtd_info {
+    int32_t nx, ny, nz, pitch;   /* pitch: floats between x rows on device   */
+    double sx, sy, sz;           /* S Δx/Δ_d                                  */
+    double k, beta, kr, omega;   /* normalised (1/Δx, 1/(Δx/c))              */
+    int32_t n_source[6];         /* antenna points per component per plane   */
+    int32_t n_slots;             /* antenna columns                          */
+    int32_t kernel;              /* kernel in use                            */
+    int32_t tile_rows;           /* fused kernel: y rows per wavefront        */
+    int32_t tile_zchunk;         /* fused kernel: planes per wavefront        */
+    int64_t step;                /* completed steps                           */
+    int64_t device_bytes;        /* device memory held by the context         */
+} fdtd_info;
+
+/* Library version string (static storage). */
+const char *fdtd_version(void);
+
+/* Periodic z fit (§4 sampling rule, z-periodic box): the box holds
+ * p = max(1, round(nz_hint Δx / λ_z)) whole axial periods λ_z = λ / cos θ;
+ * *nz = round(p λ_z / Δx) and *dz = p λ_z / *nz exactly (rounding half up).
+ * Pure host function; returns FDTD_EINVAL for non-positive inputs or θ
+ * outside (0, π/2). */
+int fdtd_fit_periodic_z(double wavelength, double theta, double dx, int32_t nz_hint,
+                        int32_t *nz, double *dz);
+
+/* Create a solver (§4: Yee grid, CPML on x/y, periodic z). Validates the
+ * grid (sizes, Courant condition, CPML thickness) before touching the GPU,
+ * then allocates the ping-pong field and CPML buffers on the current HIP
+ * device and zeroes them. On success *out owns everything; free it with
+ * fdtd_destroy. On failure *out is NULL. */
+int fdtd_create(const fdtd_grid *grid, fdtd_ctx **out);
+
+/* Free the context and all its device memory. NULL-safe. */
+int fdtd_destroy(fdtd_ctx *ctx);
+
+/* Message of the last failure on ctx (or of the last failed fdtd_create when
+ * ctx is NULL). Static or context-owned storage; valid until the next call. */
+const char *fdtd_last_error(const fdtd_ctx *ctx);
+
+/* Install the Bessel antenna (§3.1 TE fields of the Π_x potential, §4 antenna
+ * and soft source): every component location with R_B - δs < r <= R_B from
+ * the axis becomes a source point for the whole z length; its complex
+ * amplitude Ã_c (Ẽ = i (E0/k) Q, H̃ = (E0/k²) R) is computed in double
+ * precision, J_ν from std::cyl_bessel_j. Each step adds
+ * Re{w_s Ã_c e^{iβ z_c} f(t) e^{-iω(t - T0)}} to that component. With
+ * n_sectors > 0 the weight w_s = a_s e^{iφ_s} of the sector
+ * s = floor(n_sectors φ_c / 2π) of the point's azimuth multiplies Ã_c.
+ * Requires an integer number of axial periods in the box (|β nz Δz / 2π -
+ * round| <= 1e-6). inj == NULL removes the antenna. */
+int fdtd_set_injector(fdtd_ctx *ctx, const fdtd_injector *inj);
+
+/* Replace the sector weights of the installed antenna (host arrays of n
+ * doubles). n must equal the injector's n_sectors. */
+int fdtd_set_sector_weights(fdtd_ctx *ctx, int32_t n, const double *amp, const double *phase);
+
+/* Diagnostics (§5). For every step n >= window_begin_step (0-based step
+ * index; E^{n+1} is accumulated) the selected squares of E on plane
+ * k = k_plane are summed in double precision; fdtd_fluence returns their
+ * mean. Also resets the sums and the count. FDTD_DIAG_ENERGY records W after
+ * every step. */
+int fdtd_set_diagnostics(fdtd_ctx *ctx, int32_t k_plane, int64_t window_begin_step,
+                         uint32_t mask);
+
+/* Advance nsteps leapfrog steps on the context's stream (asynchronous). */
+int fdtd_step(fdtd_ctx *ctx, int64_t nsteps);
+
+/* Mean over the window of one plane quantity (FDTD_DIAG_EX2, _EY2 or _EZ2),
+ * written to host_out[ny*nx] (x fastest). Synchronises. n = capacity. */
+int fdtd_fluence(fdtd_ctx *ctx, uint32_t quantity, float *host_out, int64_t n);
+
+/* Number of steps accumulated in the fluence sums. */
+int fdtd_fluence_count(const fdtd_ctx *ctx, int64_t *count);
+
+/* W after the most recent step (FDTD_DIAG_ENERGY must be on). Synchronises;
+ * returns FDTD_EUNSTABLE if W is not finite. */
+int fdtd_energy(fdtd_ctx *ctx, double *out);
+
+/* Copy one state array (FDTD_EX .. FDTD_PSI_HZY) to / from the host; n is
+ * the element count of the host array and must match the array's size
+ * (nz*ny*nx for fields, the slab sizes above for ψ). Synchronises. */
+int fdtd_get_state(fdtd_ctx *ctx, int32_t which, float *host, int64_t n);
+int fdtd_set_state(fdtd_ctx *ctx, int32_t which, const float *host, int64_t n);
+
+/* Zero fields, CPML memories, diagnostics and the step counter. */
+int fdtd_reset(fdtd_ctx *ctx);
+
+/* Sizes, derived constants, antenna counts, kernel choice. */
+int fdtd_get_info(const fdtd_ctx *ctx, fdtd_info *out);
+
+/* Analytic reference on the diagnostic plane: ½ E0² cos²θ J_m²(K r) at the
+ * E_y positions (the time average of E_y² of the CW beam, §3.1/§5), written
+ * to host_out[ny*nx]. Requires an injector. */
+int fdtd_analytic_ey2(fdtd_ctx *ctx, float *host_out, int64_t n);
+
+/* Select the fused kernel's tile shape explicitly (rows per wavefront in
+ * {4, 8}; z chunk in planes, 0 = whole z). Returns FDTD_EINVAL otherwise. */
+int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
+
+/* Time candidate tile shapes on the live problem (the state is restored) and
+ * keep the fastest. *best_rows / *best_zchunk may be NULL. */
+int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,
+                  int32_t *best_zchunk);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BESSELFDTD_FDTD_H */

@@ -1,0 +1,620 @@
+// C ABI of the Bessel-antenna FDTD solver: context life cycle, device
+// buffers, antenna tables, the step loop and read-backs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fdtd_internal.hpp"
+
+using namespace bfdtd;
+
+namespace bfdtd {
+int split_partial_count(const Problem& p);
+}
+
+struct fdtd_ctx {
+    fdtd_grid g{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double ry = 1, rz = 1;
+    Problem p{};
+    std::vector<void*> allocs;
+    long long device_bytes = 0;
+    // antenna
+    bool has_inj = false;
+    Antenna ant;
+    int* colmap = nullptr;
+    float2* amp = nullptr;
+    float2* zph = nullptr;
+    float2* tE = nullptr;
+    float2* tH = nullptr;
+    long long t_cap = 0;
+    // diagnostics
+    int plane = -1;
+    long long wbegin = 0;
+    unsigned mask = 0;
+    long long count = 0;
+    double* fl = nullptr;
+    double* epart = nullptr;
+    int epart_cap = 0;
+    double* energy_dev = nullptr;
+    bool energy_valid = false;
+    // stepping
+    long long step = 0;
+    int parity = 0;
+    int kernel = FDTD_KERNEL_FUSED;
+    int rows = 8, zchunk = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+const char* kVersion = "besselfdtd 0.1 (gfx950)";
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+void check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? FDTD_ENOMEM
+                                                                              : FDTD_EDEVICE;
+        throw Fail{code, std::string(what) + ": " + hipGetErrorString(e)};
+    }
+}
+
+template <typename T>
+T* dalloc(fdtd_ctx* c, size_t count) {
+    if (count == 0) return nullptr;
+    void* ptr = nullptr;
+    check(hipMalloc(&ptr, count * sizeof(T)), "hipMalloc");
+    c->allocs.push_back(ptr);
+    c->device_bytes += (long long)(count * sizeof(T));
+    check(hipMemsetAsync(ptr, 0, count * sizeof(T), c->stream), "hipMemsetAsync");
+    return static_cast<T*>(ptr);
+}
+
+void dfree(fdtd_ctx* c, void* ptr) {
+    if (!ptr) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), ptr);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(ptr);
+}
+
+template <typename F>
+int guarded(fdtd_ctx* c, F&& f) {
+    try {
+        f();
+        return FDTD_OK;
+    } catch (const Fail& e) {
+        if (c) c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return FDTD_ENOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected exception";
+        return FDTD_EDEVICE;
+    }
+}
+
+void need(bool ok, const std::string& msg, int code = FDTD_EINVAL) {
+    if (!ok) throw Fail{code, msg};
+}
+
+size_t state_elems(const fdtd_ctx* c, int which) {
+    const Problem& p = c->p;
+    if (which >= FDTD_EX && which <= FDTD_HZ) return (size_t)p.nz * p.ny * p.nx;
+    if (p.npml == 0) return 0;
+    switch (which) {
+        case FDTD_PSI_EYX: case FDTD_PSI_EZX: case FDTD_PSI_HYX: case FDTD_PSI_HZX:
+            return (size_t)p.nz * p.ny * 2 * p.npml;
+        default:
+            return (size_t)p.nz * 2 * p.npml * p.nx;
+    }
+}
+
+bool psi_is_x(int which) {
+    return which == FDTD_PSI_EYX || which == FDTD_PSI_EZX || which == FDTD_PSI_HYX ||
+           which == FDTD_PSI_HZX;
+}
+
+void ensure_time_tables(fdtd_ctx* c, long long upto) {
+    if (!c->has_inj || upto <= c->t_cap) return;
+    check(hipStreamSynchronize(c->stream), "sync");   // old tables may be in use
+    long long cap = std::max(upto, std::max(2 * c->t_cap, 1024LL));
+    std::vector<float2> te(cap), th(cap);
+    const double dt = c->g.courant;
+    for (long long n = 0; n < cap; ++n) {
+        double re, im;
+        time_factor(c->ant, (n + 1.0) * dt, &re, &im);
+        te[n] = make_float2((float)re, (float)im);
+        time_factor(c->ant, (n + 1.5) * dt, &re, &im);
+        th[n] = make_float2((float)re, (float)im);
+    }
+    dfree(c, c->tE);
+    dfree(c, c->tH);
+    c->tE = dalloc<float2>(c, cap);
+    c->tH = dalloc<float2>(c, cap);
+    check(hipMemcpyAsync(c->tE, te.data(), cap * sizeof(float2), hipMemcpyHostToDevice, c->stream),
+          "copy time table");
+    check(hipMemcpyAsync(c->tH, th.data(), cap * sizeof(float2), hipMemcpyHostToDevice, c->stream),
+          "copy time table");
+    check(hipStreamSynchronize(c->stream), "sync");
+    c->t_cap = cap;
+    c->p.tE = c->tE;
+    c->p.tH = c->tH;
+}
+
+int partial_count(const fdtd_ctx* c) {
+    if (c->kernel == FDTD_KERNEL_SPLIT) return split_partial_count(c->p);
+    return fused_wave_count(c->p, c->rows, c->zchunk);
+}
+
+void ensure_partials(fdtd_ctx* c) {
+    int need_n = std::max(partial_count(c), split_partial_count(c->p));
+    if (need_n <= c->epart_cap) return;
+    dfree(c, c->epart);
+    c->epart = dalloc<double>(c, need_n);
+    c->epart_cap = need_n;
+}
+
+void launch_one(fdtd_ctx* c, long long n) {
+    Problem q = c->p;
+    const bool in_window = c->plane >= 0 && n >= c->wbegin;
+    q.diag_mask = in_window ? (int)(c->mask & 7u) : 0;
+    q.plane = c->plane;
+    q.epart = (c->mask & FDTD_DIAG_ENERGY) ? c->epart : nullptr;
+    hipError_t e;
+    if (c->kernel == FDTD_KERNEL_SPLIT)
+        e = launch_split_step(q, n, c->parity, c->stream);
+    else
+        e = launch_fused_step(q, n, c->parity, c->rows, c->zchunk, c->stream);
+    check(e, "step launch");
+    if (q.epart) {
+        check(launch_energy_reduce(c->epart, partial_count(c), c->energy_dev, c->stream),
+              "energy reduce");
+        c->energy_valid = true;
+    }
+    if (q.diag_mask) c->count += 1;
+    c->parity ^= 1;
+    c->step += 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fdtd_version(void) { return kVersion; }
+
+int fdtd_fit_periodic_z(double wavelength, double theta, double dx, int32_t nz_hint, int32_t* nz,
+                        double* dz) {
+    if (!nz || !dz) return FDTD_EINVAL;
+    if (!(wavelength > 0) || !(dx > 0) || nz_hint < 1 || !(theta > 0) ||
+        !(theta < 1.5707963267948966))
+        return FDTD_EINVAL;
+    double lam_z = wavelength / std::cos(theta);
+    double p = std::max(1.0, std::floor(nz_hint * dx / lam_z + 0.5));
+    double n = std::max(1.0, std::floor(p * lam_z / dx + 0.5));
+    if (n > 2147483647.0) return FDTD_EINVAL;
+    *nz = (int32_t)n;
+    *dz = p * lam_z / n;
+    return FDTD_OK;
+}
+
+const char* fdtd_last_error(const fdtd_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
+    if (!out) return FDTD_EINVAL;
+    *out = nullptr;
+    if (!grid) {
+        g_create_error = "grid is NULL";
+        return FDTD_EINVAL;
+    }
+    std::string v = validate_grid(*grid);
+    if (!v.empty()) {
+        g_create_error = v;
+        return FDTD_EINVAL;
+    }
+    fdtd_ctx* c = new (std::nothrow) fdtd_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return FDTD_ENOMEM;
+    }
+    int rc = guarded(c, [&] {
+        int ndev = 0;
+        check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        need(ndev > 0, "no HIP device", FDTD_EDEVICE);
+        check(hipGetDevice(&c->device), "hipGetDevice");
+        c->g = *grid;
+        c->stream = (hipStream_t)grid->stream;
+        c->ry = grid->dy / grid->dx;
+        c->rz = grid->dz / grid->dx;
+        c->kernel = grid->kernel == FDTD_KERNEL_SPLIT ? FDTD_KERNEL_SPLIT : FDTD_KERNEL_FUSED;
+        Problem& p = c->p;
+        p.nx = grid->nx;
+        p.ny = grid->ny;
+        p.nz = grid->nz;
+        p.pitch = (grid->nx + 15) / 16 * 16;
+        p.npml = grid->bc_xy == FDTD_BC_CPML ? grid->cpml_cells : 0;
+        p.periodic = grid->bc_xy == FDTD_BC_PERIODIC;
+        p.plane = -1;
+        p.sx = (float)grid->courant;
+        p.sy = (float)(grid->courant / c->ry);
+        p.sz = (float)(grid->courant / c->rz);
+        p.fstride = (long long)field_elems(p);
+        need(field_elems(p) * sizeof(float) < (1ull << 32),
+             "one field component must stay below 4 GiB (32-bit offsets)");
+        if (p.npml > 0) {
+            p.psx = (long long)psix_elems(p);
+            p.psy = (long long)psiy_elems(p);
+        }
+        for (int par = 0; par < 2; ++par) {
+            p.fbase[par] = dalloc<float>(c, 6 * field_elems(p));
+            p.pbase[par] = p.npml > 0 ? dalloc<float>(c, psi_total(p)) : nullptr;
+        }
+        std::vector<float> tx[6], ty[6];
+        cpml_axis_tables(p.nx, p.npml, 1.0, *grid, grid->courant, tx);
+        cpml_axis_tables(p.ny, p.npml, c->ry, *grid, grid->courant, ty);
+        std::vector<float> tab;
+        for (int t = 0; t < 6; ++t) tab.insert(tab.end(), tx[t].begin(), tx[t].end());
+        for (int t = 0; t < 6; ++t) tab.insert(tab.end(), ty[t].begin(), ty[t].end());
+        float* tabs = dalloc<float>(c, tab.size());
+        check(hipMemcpyAsync(tabs, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream), "copy cpml");
+        p.ctab = tabs;
+        c->fl = dalloc<double>(c, 3 * (size_t)p.nx * p.ny);
+        p.fl = c->fl;
+        c->energy_dev = dalloc<double>(c, 1);
+        ensure_partials(c);
+        check(hipStreamSynchronize(c->stream), "sync");
+    });
+    if (rc != FDTD_OK) {
+        g_create_error = c->err;
+        fdtd_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return FDTD_OK;
+}
+
+int fdtd_destroy(fdtd_ctx* ctx) {
+    if (!ctx) return FDTD_OK;
+    if (!ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (void* ptr : ctx->allocs) (void)hipFree(ptr);
+    delete ctx;
+    return FDTD_OK;
+}
+
+int fdtd_set_injector(fdtd_ctx* c, const fdtd_injector* inj) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        if (!inj) {
+            check(hipStreamSynchronize(c->stream), "sync");
+            dfree(c, c->colmap); dfree(c, c->amp); dfree(c, c->zph);
+            dfree(c, c->tE); dfree(c, c->tH);
+            c->colmap = nullptr; c->amp = nullptr; c->zph = nullptr;
+            c->tE = c->tH = nullptr;
+            c->t_cap = 0;
+            c->has_inj = false;
+            c->p.colmap = nullptr; c->p.amp = nullptr; c->p.zph = nullptr;
+            c->p.tE = c->p.tH = nullptr;
+            c->p.n_slots = 0;
+            return;
+        }
+        Antenna a;
+        std::string msg = build_antenna(c->g, c->p.pitch, c->ry, c->rz, *inj, &a);
+        need(msg.empty(), msg);
+        check(hipStreamSynchronize(c->stream), "sync");
+        dfree(c, c->colmap); dfree(c, c->amp); dfree(c, c->zph);
+        dfree(c, c->tE); dfree(c, c->tH);
+        c->tE = c->tH = nullptr;
+        c->t_cap = 0;
+        c->ant = std::move(a);
+        const Problem& p = c->p;
+        const int ns = (int)c->ant.slot_i.size();
+        std::vector<int> map((size_t)p.nx * p.ny, -1);
+        for (int s = 0; s < ns; ++s) map[(size_t)c->ant.slot_j[s] * p.nx + c->ant.slot_i[s]] = s;
+        std::vector<float> amp;
+        weighted_amplitudes(c->ant, &amp);
+        std::vector<float2> zph(2 * (size_t)p.nz);
+        for (int k = 0; k < p.nz; ++k) {
+            double z0 = c->ant.beta * k * c->rz, z1 = c->ant.beta * (k + 0.5) * c->rz;
+            zph[2 * k] = make_float2((float)std::cos(z0), (float)std::sin(z0));
+            zph[2 * k + 1] = make_float2((float)std::cos(z1), (float)std::sin(z1));
+        }
+        c->colmap = dalloc<int>(c, map.size());
+        c->amp = dalloc<float2>(c, std::max<size_t>(1, (size_t)ns * 6));
+        c->zph = dalloc<float2>(c, zph.size());
+        check(hipMemcpyAsync(c->colmap, map.data(), map.size() * sizeof(int),
+                             hipMemcpyHostToDevice, c->stream), "copy map");
+        if (ns > 0)
+            check(hipMemcpyAsync(c->amp, amp.data(), amp.size() * sizeof(float),
+                                 hipMemcpyHostToDevice, c->stream), "copy amp");
+        check(hipMemcpyAsync(c->zph, zph.data(), zph.size() * sizeof(float2),
+                             hipMemcpyHostToDevice, c->stream), "copy zph");
+        c->p.colmap = c->colmap;
+        c->p.amp = c->amp;
+        c->p.zph = c->zph;
+        c->p.n_slots = ns;
+        c->has_inj = true;
+        ensure_time_tables(c, c->step + 1024);
+    });
+}
+
+int fdtd_set_sector_weights(fdtd_ctx* c, int32_t n, const double* amp, const double* phase) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(c->has_inj, "no injector", FDTD_ESTATE);
+        need(n == c->ant.n_sectors && n > 0 && amp && phase, "sector count mismatch");
+        for (int s = 0; s < n; ++s) {
+            c->ant.sec_amp[s] = amp[s];
+            c->ant.sec_phase[s] = phase[s];
+        }
+        std::vector<float> w;
+        weighted_amplitudes(c->ant, &w);
+        if (!w.empty())
+            check(hipMemcpyAsync(c->amp, w.data(), w.size() * sizeof(float),
+                                 hipMemcpyHostToDevice, c->stream), "copy amp");
+        check(hipStreamSynchronize(c->stream), "sync");
+    });
+}
+
+int fdtd_set_diagnostics(fdtd_ctx* c, int32_t k_plane, int64_t window_begin_step, uint32_t mask) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(k_plane >= -1 && k_plane < c->p.nz, "plane out of range");
+        need(window_begin_step >= 0, "window begin must be >= 0");
+        need((mask & ~15u) == 0, "unknown diagnostics bits");
+        need(k_plane >= 0 || (mask & 7u) == 0, "plane quantities need a plane");
+        c->plane = k_plane;
+        c->wbegin = window_begin_step;
+        c->mask = mask;
+        c->count = 0;
+        c->energy_valid = false;
+        check(hipMemsetAsync(c->fl, 0, 3 * (size_t)c->p.nx * c->p.ny * sizeof(double), c->stream),
+              "clear fluence");
+        ensure_partials(c);
+    });
+}
+
+int fdtd_step(fdtd_ctx* c, int64_t nsteps) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(nsteps >= 0, "nsteps must be >= 0");
+        ensure_time_tables(c, c->step + nsteps);
+        ensure_partials(c);
+        for (int64_t s = 0; s < nsteps; ++s) launch_one(c, c->step);
+    });
+}
+
+int fdtd_fluence(fdtd_ctx* c, uint32_t quantity, float* host_out, int64_t n) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        int ch = quantity == FDTD_DIAG_EX2 ? 0 : quantity == FDTD_DIAG_EY2 ? 1
+               : quantity == FDTD_DIAG_EZ2 ? 2 : -1;
+        need(ch >= 0, "quantity must be one of FDTD_DIAG_EX2/EY2/EZ2");
+        const size_t np = (size_t)c->p.nx * c->p.ny;
+        need(host_out && n >= (int64_t)np, "output buffer too small");
+        std::vector<double> h(np);
+        check(hipMemcpyAsync(h.data(), c->fl + ch * np, np * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream), "copy fluence");
+        check(hipStreamSynchronize(c->stream), "sync");
+        const double inv = c->count > 0 ? 1.0 / (double)c->count : 0.0;
+        for (size_t q = 0; q < np; ++q) host_out[q] = (float)(h[q] * inv);
+    });
+}
+
+int fdtd_fluence_count(const fdtd_ctx* c, int64_t* count) {
+    if (!c || !count) return FDTD_EINVAL;
+    *count = c->count;
+    return FDTD_OK;
+}
+
+int fdtd_energy(fdtd_ctx* c, double* out) {
+    if (!c || !out) return FDTD_EINVAL;
+    int rc = guarded(c, [&] {
+        need(c->energy_valid, "energy diagnostics not enabled or no step taken", FDTD_ESTATE);
+        check(hipMemcpyAsync(out, c->energy_dev, sizeof(double), hipMemcpyDeviceToHost, c->stream),
+              "copy energy");
+        check(hipStreamSynchronize(c->stream), "sync");
+    });
+    if (rc == FDTD_OK && !std::isfinite(*out)) {
+        c->err = "energy is not finite";
+        return FDTD_EUNSTABLE;
+    }
+    return rc;
+}
+
+int fdtd_get_state(fdtd_ctx* c, int32_t which, float* host, int64_t n) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(which >= FDTD_EX && which <= FDTD_PSI_HZY, "unknown state array");
+        size_t ne = state_elems(c, which);
+        need(ne > 0, "array not present (no CPML)");
+        need(host && n == (int64_t)ne, "element count mismatch");
+        const Problem& p = c->p;
+        if (which <= FDTD_HZ) {
+            check(hipMemcpy2DAsync(host, p.nx * sizeof(float), p.fbase[c->parity] + which * p.fstride,
+                                   p.pitch * sizeof(float), p.nx * sizeof(float),
+                                   (size_t)p.nz * p.ny, hipMemcpyDeviceToHost, c->stream),
+                  "copy field");
+        } else if (psi_is_x(which)) {
+            check(hipMemcpyAsync(host, p.pbase[c->parity] + psi_offset(p, which - FDTD_PSI_EXY),
+                                 ne * sizeof(float),
+                                 hipMemcpyDeviceToHost, c->stream), "copy psi");
+        } else {
+            check(hipMemcpy2DAsync(host, p.nx * sizeof(float),
+                                   p.pbase[c->parity] + psi_offset(p, which - FDTD_PSI_EXY),
+                                   p.pitch * sizeof(float), p.nx * sizeof(float),
+                                   (size_t)p.nz * 2 * p.npml, hipMemcpyDeviceToHost, c->stream),
+                  "copy psi");
+        }
+        check(hipStreamSynchronize(c->stream), "sync");
+    });
+}
+
+int fdtd_set_state(fdtd_ctx* c, int32_t which, const float* host, int64_t n) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(which >= FDTD_EX && which <= FDTD_PSI_HZY, "unknown state array");
+        size_t ne = state_elems(c, which);
+        need(ne > 0, "array not present (no CPML)");
+        need(host && n == (int64_t)ne, "element count mismatch");
+        const Problem& p = c->p;
+        if (which <= FDTD_HZ) {
+            check(hipMemcpy2DAsync(p.fbase[c->parity] + which * p.fstride, p.pitch * sizeof(float), host,
+                                   p.nx * sizeof(float), p.nx * sizeof(float), (size_t)p.nz * p.ny,
+                                   hipMemcpyHostToDevice, c->stream), "copy field");
+        } else if (psi_is_x(which)) {
+            check(hipMemcpyAsync(p.pbase[c->parity] + psi_offset(p, which - FDTD_PSI_EXY), host,
+                                 ne * sizeof(float),
+                                 hipMemcpyHostToDevice, c->stream), "copy psi");
+        } else {
+            check(hipMemcpy2DAsync(p.pbase[c->parity] + psi_offset(p, which - FDTD_PSI_EXY),
+                                   p.pitch * sizeof(float),
+                                   host, p.nx * sizeof(float), p.nx * sizeof(float),
+                                   (size_t)p.nz * 2 * p.npml, hipMemcpyHostToDevice, c->stream),
+                  "copy psi");
+        }
+        check(hipStreamSynchronize(c->stream), "sync");
+        c->energy_valid = false;
+    });
+}
+
+int fdtd_reset(fdtd_ctx* c) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        const Problem& p = c->p;
+        for (int par = 0; par < 2; ++par) {
+            check(hipMemsetAsync(p.fbase[par], 0, 6 * field_elems(p) * sizeof(float), c->stream),
+                  "clear");
+            if (p.npml > 0)
+                check(hipMemsetAsync(p.pbase[par], 0, psi_total(p) * sizeof(float), c->stream),
+                      "clear");
+        }
+        check(hipMemsetAsync(c->fl, 0, 3 * (size_t)p.nx * p.ny * sizeof(double), c->stream),
+              "clear");
+        check(hipStreamSynchronize(c->stream), "sync");
+        c->step = 0;
+        c->parity = 0;
+        c->count = 0;
+        c->energy_valid = false;
+    });
+}
+
+int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
+    if (!c || !out) return FDTD_EINVAL;
+    std::memset(out, 0, sizeof *out);
+    out->nx = c->p.nx;
+    out->ny = c->p.ny;
+    out->nz = c->p.nz;
+    out->pitch = c->p.pitch;
+    out->sx = c->g.courant;
+    out->sy = c->g.courant / c->ry;
+    out->sz = c->g.courant / c->rz;
+    if (c->has_inj) {
+        out->k = c->ant.k;
+        out->beta = c->ant.beta;
+        out->kr = c->ant.kr;
+        out->omega = c->ant.omega;
+        for (int q = 0; q < 6; ++q) out->n_source[q] = c->ant.n_source[q];
+        out->n_slots = (int32_t)c->ant.slot_i.size();
+    }
+    out->kernel = c->kernel;
+    out->tile_rows = c->rows;
+    out->tile_zchunk = c->zchunk;
+    out->step = c->step;
+    out->device_bytes = c->device_bytes;
+    return FDTD_OK;
+}
+
+int fdtd_analytic_ey2(fdtd_ctx* c, float* host_out, int64_t n) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(c->has_inj, "no injector", FDTD_ESTATE);
+        const Problem& p = c->p;
+        need(host_out && n >= (int64_t)p.nx * p.ny, "output buffer too small");
+        const Antenna& a = c->ant;
+        const double amp = 0.5 * a.e0 * a.e0 * std::cos(a.theta) * std::cos(a.theta);
+        for (int j = 0; j < p.ny; ++j) {
+            for (int i = 0; i < p.nx; ++i) {
+                double r = std::hypot(i - a.ax, (j + 0.5) * c->ry - a.ay);
+                double v = std::cyl_bessel_j((double)a.order, a.kr * r);
+                host_out[(size_t)j * p.nx + i] = (float)(amp * v * v);
+            }
+        }
+    });
+}
+
+int fdtd_set_tile(fdtd_ctx* c, int32_t rows, int32_t zchunk) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(rows == 4 || rows == 8, "rows must be 4 or 8");
+        need(zchunk >= 0 && zchunk <= c->p.nz, "zchunk out of range");
+        c->rows = rows;
+        c->zchunk = zchunk;
+        ensure_partials(c);
+    });
+}
+
+int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
+                  int32_t* best_zchunk) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(steps_per_trial >= 1 && steps_per_trial <= 1000, "steps_per_trial out of range");
+        need(c->kernel == FDTD_KERNEL_FUSED, "autotune applies to the fused kernel");
+        ensure_time_tables(c, c->step + 1);
+        // Trials read the live parity buffer and write the other one, which
+        // the next real step overwrites: the state is left as it was.
+        Problem q = c->p;
+        q.diag_mask = 0;
+        q.epart = nullptr;
+        q.rec = nullptr;
+        const int nz = c->p.nz;
+        std::vector<int> chunks = {0};
+        for (int d = 2; d <= 16; d *= 2)
+            if (nz / d >= 8) chunks.push_back((nz + d - 1) / d);
+        hipEvent_t e0, e1;
+        check(hipEventCreate(&e0), "event");
+        check(hipEventCreate(&e1), "event");
+        float best = 1e30f;
+        int br = c->rows, bz = c->zchunk;
+        for (int rows : {4, 8}) {
+            for (int cz : chunks) {
+                check(launch_fused_step(q, c->step, c->parity, rows, cz, c->stream), "trial");
+                check(hipEventRecord(e0, c->stream), "event");
+                for (int s = 0; s < steps_per_trial; ++s)
+                    check(launch_fused_step(q, c->step, c->parity, rows, cz, c->stream), "trial");
+                check(hipEventRecord(e1, c->stream), "event");
+                check(hipEventSynchronize(e1), "event");
+                float ms = 0.f;
+                check(hipEventElapsedTime(&ms, e0, e1), "event");
+                if (ms < best) {
+                    best = ms;
+                    br = rows;
+                    bz = cz;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->rows = br;
+        c->zchunk = bz;
+        ensure_partials(c);
+        if (best_rows) *best_rows = br;
+        if (best_zchunk) *best_zchunk = bz;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal types shared by the host set-up, the C ABI and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+
+namespace bfdtd {
+
+enum { EX = 0, EY, EZ, HX, HY, HZ };
+// CPML memories: ψ of (component, derivative axis)
+enum { P_EXY = 0, P_EYX, P_EZX, P_EZY, P_HXY, P_HYX, P_HZX, P_HZY };
+// 1-D CPML tables: b, c, 1/κ at integer (E) and half-integer (H) positions
+enum { T_EB = 0, T_EC, T_EK, T_HB, T_HC, T_HK };
+
+// Everything a kernel needs to advance one problem instance. Plain data,
+// passed by value to single-domain launches and read from device memory by
+// the batched persistent kernel. Few pointers on purpose: every field of one
+// parity lives in one allocation (component c at fbase[par] + c*fstride), the
+// eight CPML memories of one parity in another (x-slab arrays first), and
+// the twelve CPML coefficient rows in a third.
+struct Problem {
+    int nx, ny, nz, pitch;          // pitch: floats per x row
+    int npml;                       // CPML cells (0: none)
+    int periodic;                   // x/y periodic test mode
+    int plane;                      // diagnostic plane, -1: none
+    int diag_mask;                  // FDTD_DIAG_* bits accumulated this step
+    float sx, sy, sz;               // S Δx/Δ_d
+    int n_slots;
+    float* fbase[2];                // ping-pong fields [parity]
+    long long fstride;              // floats per component (nz*ny*pitch)
+    float* pbase[2];                // ping-pong CPML memories [parity]
+    long long psx;                  // floats per x-slab array (nz*ny*2*npml)
+    long long psy;                  // floats per y-slab array (nz*2*npml*pitch)
+    const float* ctab;              // [6][nx] x tables then [6][ny] y tables
+    const int* colmap;              // [ny][nx] antenna slot or -1
+    const float2* amp;              // [slot][6] w·Ã (FP32 from FP64)
+    const float2* zph;              // [nz][2] e^{iβ z} at integer / half planes
+    const float2* tE;               // [step] f(t_{n+1}) e^{-iω(t_{n+1}-T0)}
+    const float2* tH;               // [step] f(t_{n+3/2}) e^{-iω(t_{n+3/2}-T0)}
+    double* fl;                     // [3][ny][nx] plane sums (E_x², E_y², E_z²)
+    double* epart;                  // energy partial sums, one per wavefront
+    float* rec;                     // E_y plane record (adjoint), or null
+    long long rec_begin;            // first recorded step
+};
+
+// Position of CPML memory q (P_* order) inside one parity's allocation.
+__host__ __device__ inline long long psi_offset(const Problem& p, int q) {
+    switch (q) {
+        case P_EYX: return 0;
+        case P_EZX: return p.psx;
+        case P_HYX: return 2 * p.psx;
+        case P_HZX: return 3 * p.psx;
+        case P_EXY: return 4 * p.psx;
+        case P_EZY: return 4 * p.psx + p.psy;
+        case P_HXY: return 4 * p.psx + 2 * p.psy;
+        default:    return 4 * p.psx + 3 * p.psy;   // P_HZY
+    }
+}
+
+inline size_t field_elems(const Problem& p) { return (size_t)p.nz * p.ny * p.pitch; }
+inline size_t psix_elems(const Problem& p) { return (size_t)p.nz * p.ny * 2 * p.npml; }
+inline size_t psiy_elems(const Problem& p) { return (size_t)p.nz * 2 * p.npml * p.pitch; }
+inline size_t psi_total(const Problem& p) { return 4 * psix_elems(p) + 4 * psiy_elems(p); }
+
+// Host-side antenna description (double precision).
+struct Antenna {
+    double k = 0, beta = 0, kr = 0, omega = 0, t0 = 0;
+    int ramp_kind = FDTD_RAMP_SIN2;
+    double ramp_a = 0, ramp_b = 0;       // normalised time units
+    double e0 = 1;
+    int order = 0;
+    double theta = 0;
+    double ax = 0, ay = 0, r_in = 0, r_out = 0;
+    int n_sectors = 0;
+    std::vector<double> sec_amp, sec_phase;
+    // per slot: column and, per component, base amplitude and sector
+    std::vector<int> slot_i, slot_j;
+    std::vector<double> base_re, base_im;   // [slot*6 + c]
+    std::vector<int> member;                // [slot*6 + c] 1 if a source point
+    std::vector<int> sector;                // [slot*6 + c]
+    int n_source[6] = {0, 0, 0, 0, 0, 0};
+};
+
+// Time factor f(t) e^{-iω(t - T0)} in double precision.
+void time_factor(const Antenna& a, double t, double* re, double* im);
+
+// Build the antenna (membership, amplitudes) for a grid. Returns an error
+// message or empty on success.
+std::string build_antenna(const fdtd_grid& g, int pitch, double ry, double rz,
+                          const fdtd_injector& inj, Antenna* out);
+
+// Weighted FP32 amplitudes [slot][6] as interleaved (re, im).
+void weighted_amplitudes(const Antenna& a, std::vector<float>* out);
+
+// CPML 1-D tables (b, c, 1/κ) at E and H positions along one axis.
+void cpml_axis_tables(int n, int npml, double delta_ratio, const fdtd_grid& g, double dt,
+                      std::vector<float>* tabs /* 6 vectors of n */);
+
+std::string validate_grid(const fdtd_grid& g);
+
+// Kernel launchers (kernels_*.hip)
+hipError_t launch_split_step(const Problem& p, long long n, int parity, hipStream_t s);
+hipError_t launch_fused_step(const Problem& p, long long n, int parity, int rows, int zchunk,
+                             hipStream_t s);
+int fused_wave_count(const Problem& p, int rows, int zchunk);
+hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
+
+}  // namespace bfdtd

@@ -1,0 +1,56 @@
+// Device helpers shared by the Yee kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fdtd_internal.hpp"
+
+namespace bfdtd {
+
+// CPML slab index of an x position (-1 outside the slabs).
+__device__ __forceinline__ int slab_index(int i, int n, int npml) {
+    if (npml <= 0) return -1;
+    if (i < npml) return i;
+    if (i >= n - npml) return i - n + 2 * npml;
+    return -1;
+}
+
+__device__ __forceinline__ size_t psix_at(const Problem& p, int k, int j, int xs) {
+    return ((size_t)k * p.ny + j) * (2 * p.npml) + xs;
+}
+
+__device__ __forceinline__ size_t psiy_at(const Problem& p, int k, int ys, int i) {
+    return ((size_t)k * (2 * p.npml) + ys) * p.pitch + i;
+}
+
+__device__ __forceinline__ float* fptr(const Problem& p, int par, int c) {
+    return p.fbase[par] + c * p.fstride;
+}
+
+__device__ __forceinline__ float* pptr(const Problem& p, int par, int q) {
+    return p.pbase[par] + psi_offset(p, q);
+}
+
+__device__ __forceinline__ const float* cx_tab(const Problem& p, int t) {
+    return p.ctab + (size_t)t * p.nx;
+}
+
+__device__ __forceinline__ const float* cy_tab(const Problem& p, int t) {
+    return p.ctab + (size_t)6 * p.nx + (size_t)t * p.ny;
+}
+
+// Re{a · b}
+__device__ __forceinline__ float cmul_re(float2 a, float2 b) { return a.x * b.x - a.y * b.y; }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Sum over a wave64 (deterministic butterfly order).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace bfdtd

@@ -1,0 +1,201 @@
+"""GPU parity: the HIP solver (through the C ABI) against the FP64 oracle.
+
+Tolerance: relative L2 over all six field components ≤ 1e-4 (FP32 solver
+against an FP64 reference on the same seeded inputs); CPML memories are
+compared with the same bound.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import problem as P
+from oracle import yee as Y
+from paper_2102_12978_amd import _lib as L
+from paper_2102_12978_amd import workloads as W
+from tests import cases
+from tests import gpu_cases as GC
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def _compare(s, st, g, psi=True):
+    gpu = s.fields()
+    ref = [st.f[c] for c in GC.COMPS]
+    rel = GC.rel_l2(gpu, ref)
+    per = {c: GC.rel_l2([a], [b]) for c, a, b in zip(GC.COMPS, gpu, ref)}
+    print(f"  rel-L2 all = {rel:.3e}; per component " +
+          ", ".join(f"{c}={v:.1e}" for c, v in per.items()), flush=True)
+    assert rel <= TOL, per
+    if psi and g.bc == P.BC_CPML:
+        gp, rp = [], []
+        for which, name in GC.PSI.items():
+            gp.append(s.get_state(which))
+            rp.append(GC.psi_slab(st.psi[name], which, g.npml, g.nx, g.ny))
+        prel = GC.rel_l2(gp, rp)
+        print(f"  psi rel-L2 = {prel:.3e}", flush=True)
+        assert prel <= TOL
+    return rel
+
+
+@pytest.mark.parametrize("kernel", [L.KERNEL_SPLIT, L.KERNEL_FUSED])
+def test_config0_forward(kernel):
+    """32³, Δx = λ/16, θ = 10°, m = 0, annulus 12Δx, 8-cell CPML, 200 steps."""
+    w = W.config0()
+    s = GC.gpu_solver(w, kernel=kernel)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
+@pytest.mark.parametrize("rows,zchunk", [(4, 0), (8, 0), (4, 7), (8, 13)])
+def test_ragged_tiles_with_cpml_and_source(rows, zchunk):
+    """100×72 grid (ragged in x and y for every tile shape), z chunks that do
+    not divide nz, 10-cell CPML, order-1 source, 60 steps."""
+    w = W.parity_small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=rows, zchunk=zchunk)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
+def test_split_ragged():
+    w = W.parity_small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
+@pytest.mark.parametrize("bc", [P.BC_PERIODIC, P.BC_PEC])
+@pytest.mark.parametrize("kernel", [L.KERNEL_SPLIT, L.KERNEL_FUSED])
+def test_random_start_no_source(bc, kernel):
+    """Seed-0 U(-1,1) fields, no source: periodic box (config 0 random run)
+    and PEC walls. Checks the fields, the energy invariant and div H."""
+    w = W.config0()
+    g, st0 = GC.random_start(w, bc)
+    s = GC.gpu_solver(w, kernel=kernel, bc=bc, inject=False)
+    for i, c in enumerate(GC.COMPS):
+        s.set_state(i, st0.f[c])
+    s.set_diagnostics(-1, 0, L.DIAG_ENERGY)
+    dh0 = Y.div_h(st0, g)
+    st = st0.copy()
+    cp = P.cpml_tables(g)
+    w_ref = []
+    energies = []
+    for _ in range(w.steps):
+        w_ref.append(Y.step(st, g, cp, None, want_energy=True))
+        s.step(1)
+        energies.append(s.energy())
+    _compare(s, st, g, psi=False)
+    w_ref = np.array(w_ref)
+    energies = np.array(energies)
+    drift = np.abs(energies - energies[0]).max() / abs(energies[0])
+    print(f"  energy drift (FP32 solver) = {drift:.2e}; oracle drift = "
+          f"{np.abs(w_ref - w_ref[0]).max() / abs(w_ref[0]):.1e}", flush=True)
+    assert drift < 1e-5
+    assert np.abs(energies - w_ref).max() / abs(w_ref[0]) < 1e-5
+    gst = Y.zero_state(g)
+    for i, c in enumerate(GC.COMPS):
+        gst.f[c] = s.get_state(i).astype(np.float64)
+    ddiv = np.abs(Y.div_h(gst, g) - dh0).max()
+    print(f"  max |div H - div H0| = {ddiv:.2e}", flush=True)
+    assert ddiv < 1e-4
+    s.close()
+
+
+def test_random_start_with_source_and_cpml():
+    """Random start (walls zeroed) plus the antenna and CPML: the general
+    state including nonzero CPML memories from the first step."""
+    w = W.parity_small()
+    w.steps = 40
+    g, st0 = GC.random_start(w, P.BC_CPML, seed=4)
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    for i, c in enumerate(GC.COMPS):
+        s.set_state(i, st0.f[c])
+    s.step(w.steps)
+    _, st = GC.oracle_run(w, w.steps, state=st0)
+    _compare(s, st, g)
+    s.close()
+
+
+def test_plane_diagnostics_and_energy():
+    """⟨E_x²⟩, ⟨E_y²⟩, ⟨E_z²⟩ on the mid plane over a window, and W^n."""
+    w = W.parity_small()
+    w.steps = 50
+    g = cases.oracle_grid(w)
+    plane, wb = g.nz // 2, 30
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=9)
+    s.set_diagnostics(plane, wb, L.DIAG_EX2 | L.DIAG_EY2 | L.DIAG_EZ2 | L.DIAG_ENERGY)
+    s.step(w.steps)
+    d = Y.Diag(plane=plane, window_begin=wb)
+    _, st = GC.oracle_run(w, w.steps, diag=d, energy=True)
+    assert s.fluence_count() == d.count == w.steps - wb
+    for q, key in ((L.DIAG_EX2, "ex2"), (L.DIAG_EY2, "ey2"), (L.DIAG_EZ2, "ez2")):
+        rel = GC.rel_l2([s.fluence(q)], [d.mean(key)])
+        print(f"  {key} rel-L2 = {rel:.2e}", flush=True)
+        assert rel <= TOL
+    e = s.energy()
+    print(f"  energy {e:.9e} vs {d.energy[-1]:.9e}", flush=True)
+    assert abs(e - d.energy[-1]) <= 1e-4 * abs(d.energy[-1])
+    s.close()
+
+
+def test_fused_equals_split():
+    w = W.parity_small()
+    a = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
+    b = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=8, zchunk=0)
+    a.step(w.steps)
+    b.step(w.steps)
+    rel = GC.rel_l2(b.fields(), [x.astype(np.float64) for x in a.fields()])
+    print(f"  fused vs split rel-L2 = {rel:.2e}", flush=True)
+    assert rel < 1e-5
+    a.close()
+    b.close()
+
+
+def test_state_roundtrip_and_reset():
+    w = W.parity_small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    rng = np.random.default_rng(5)
+    for which in list(range(6)) + list(GC.PSI):
+        a = rng.standard_normal(s.state_shape(which)).astype(np.float32)
+        s.set_state(which, a)
+        assert np.array_equal(s.get_state(which), a)
+    s.reset()
+    assert s.info().step == 0
+    assert all(np.count_nonzero(s.get_state(c)) == 0 for c in range(6))
+    s.close()
+
+
+def test_autotune_leaves_state_alone():
+    w = W.parity_small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    s.step(20)
+    rows, zc = s.autotune(2)
+    print(f"  autotune picked rows={rows} zchunk={zc}", flush=True)
+    assert rows in (4, 8)
+    s.step(w.steps - 20)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
+def test_source_linearity_on_gpu():
+    w = W.parity_small()
+    w.steps = 30
+    a = GC.gpu_solver(w)
+    w2 = W.parity_small()
+    w2.steps = 30
+    w2.e0 = 2.0
+    b = GC.gpu_solver(w2)
+    a.step(30)
+    b.step(30)
+    rel = GC.rel_l2(b.fields(), [2.0 * x.astype(np.float64) for x in a.fields()])
+    assert rel < 1e-6
+    a.close()
+    b.close()

@@ -1,0 +1,72 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every symbol the header declares, and its pure host logic (periodic z fit,
+argument validation) behaves."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from oracle import problem as P
+from paper_2102_12978_amd import _lib as L
+from paper_2102_12978_amd.solver import Solver, fit_periodic_z
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    declared = L.declared_symbols()
+    assert len(declared) >= 19
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.fdtd_version().startswith(b"besselfdtd")
+
+
+@pytest.mark.parametrize("theta_deg,ns,hint", [(10, 16, 32), (15, 20, 64), (20, 24, 256),
+                                               (12, 20, 64), (5, 20, 48), (30, 20, 64),
+                                               (25, 16, 18), (30, 16, 1)])
+def test_fit_periodic_z_matches_reference(theta_deg, ns, hint):
+    lam = 800e-9
+    nz, dz = fit_periodic_z(lam, math.radians(theta_deg), lam / ns, hint)
+    nz_o, dz_o = P.fit_periodic_z(lam, math.radians(theta_deg), lam / ns, hint)
+    assert nz == nz_o
+    assert abs(dz - dz_o) <= 1e-15 * dz_o
+
+
+def test_fit_periodic_z_rejects_bad_arguments():
+    lib = L.load()
+    nz, dz = ctypes.c_int32(), ctypes.c_double()
+    for args in [(800e-9, 0.0, 5e-8, 10), (800e-9, math.pi / 2, 5e-8, 10),
+                 (-1.0, 0.3, 5e-8, 10), (800e-9, 0.3, 0.0, 10), (800e-9, 0.3, 5e-8, 0)]:
+        assert lib.fdtd_fit_periodic_z(*args, ctypes.byref(nz), ctypes.byref(dz)) == L.EINVAL
+    assert lib.fdtd_fit_periodic_z(800e-9, 0.3, 5e-8, 10, None, None) == L.EINVAL
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(courant=0.7), "Courant"),
+    (dict(cpml_cells=17), "cpml_cells"),
+    (dict(cpml_cells=0), "cpml_cells"),
+    (dict(bc=L.BC_PEC, cpml_cells=4), "cpml_cells must be 0"),
+    (dict(bc=7), "bc_xy"),
+    (dict(nx=1), "grid sizes"),
+    (dict(dz=-1.0), "cell sizes"),
+    (dict(kernel=9), "kernel"),
+])
+def test_create_validates_before_touching_the_gpu(kw, frag):
+    args = dict(nx=32, ny=32, nz=32, dx=5e-8, dy=5e-8, dz=5.07e-8, courant=0.5,
+                bc=L.BC_CPML, cpml_cells=8)
+    args.update(kw)
+    with pytest.raises(L.FdtdError) as e:
+        Solver(**args)
+    assert e.value.code == L.EINVAL
+    assert frag in str(e.value)
+
+
+def test_null_arguments_are_rejected():
+    lib = L.load()
+    assert lib.fdtd_create(None, None) == L.EINVAL
+    ctx = ctypes.c_void_p()
+    assert lib.fdtd_create(None, ctypes.byref(ctx)) == L.EINVAL
+    assert ctx.value is None
+    assert lib.fdtd_destroy(None) == L.OK
+    assert lib.fdtd_step(None, 1) == L.EINVAL
+    assert lib.fdtd_get_info(None, None) == L.EINVAL
