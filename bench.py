@@ -1,0 +1,173 @@
+"""Benchmark of the Bessel-antenna FDTD step on one MI355X.
+
+One step = one leapfrog step of the whole hot path on the 768×768×256
+(z fitted to 255) workload: E update + CPML + antenna E source, H update +
+CPML + antenna H source, mid-plane ⟨E_y²⟩ accumulation. Inputs are resident
+in HBM before timing. Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 1000] [--warmup 20] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+BYTES_PER_CELL = 48            # read + write six FP32 field components
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_interior_c2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc", "kernels_fused.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(interior_cells):
+    """HBM bytes per interior-kernel launch from the committed rocprofv3 PMC
+    summary, or None when missing or taken on another kernel source."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(w):
+    """The FP64 NumPy oracle on a bounded sample of the same workload: one
+    full step of the 768×768×255 grid (antenna and CPML included)."""
+    from oracle import problem as P
+    from oracle import yee as Y
+    nz, dz = P.fit_periodic_z(800e-9, w.theta, w.dx, w.nz_hint)
+    g = P.Grid(w.nx, w.ny, nz, w.dx, w.dx, dz, w.courant, P.BC_CPML, w.npml, w.grade,
+               w.sigma_scale, w.kappa_max, w.alpha_max)
+    inj = P.Injector(800e-9, w.theta, w.order, w.e0, w.r_outer_cells * w.dx,
+                     w.thickness_cells * w.dx, ramp_kind=P.RAMP_SIN2, ramp_a=w.ramp_seconds)
+    ant = P.build_antenna(g, inj)
+    cp = P.cpml_tables(g)
+    st = Y.zero_state(g)
+    steps = 1
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Y.step(st, g, cp, ant)
+    dt = time.perf_counter() - t0
+    cells = g.nx * g.ny * g.nz
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"value": cells * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+            "cores_available": avail, "kind": "oracle",
+            "sample": f"{steps} full step of the {g.nx}x{g.ny}x{g.nz} grid in FP64 NumPy "
+                      f"(single-threaded elementwise), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
+    ap.add_argument("--rows", type=int, default=0, help="fix the tile rows (skips autotune)")
+    ap.add_argument("--zchunk", type=int, default=0, help="z chunk with --rows")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has "
+              "no multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2102_12978_amd import _lib as L
+    from paper_2102_12978_amd import workloads as W
+    from paper_2102_12978_amd.solver import Solver
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    w = W.config2()
+    s = Solver.from_workload(w, kernel=L.KERNEL_FUSED, stream=stream.cuda_stream)
+    s.set_workload_injector(w)
+    cells = s.nx * s.ny * s.nz
+    log(f"[bench] {w.name}: {s.nx}x{s.ny}x{s.nz} = {cells / 1e6:.1f} M cells")
+    if args.rows:
+        s.set_tile(args.rows, args.zchunk)
+    elif not args.no_tune:
+        rows, zc = s.autotune(3)
+        log(f"[bench] autotuned tile: rows={rows} zchunk={zc}")
+    s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    info = s.info()
+
+    s.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    prof = s.profile_read()
+    s.profile(False)
+    ms_per_step = total_ms / args.steps
+    value = cells * args.steps / (total_ms * 1e-3) / 1e9
+    log(f"[bench] {args.steps} steps in {total_ms:.1f} ms -> {value:.1f} Gcell/s; "
+        f"kernels: {prof}")
+
+    kin = prof.get("fused_interior")
+    roof = None
+    if kin:
+        avg_ms = kin[1] / kin[0]
+        bytes_launch = BYTES_PER_CELL * info.interior_cells
+        achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic(info.interior_cells)
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "fused_interior",
+                "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": info.interior_cells,
+                "bytes_per_launch": bytes_launch}
+    step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
+    out = {
+        "metric": "Gcell-updates/s (Yee E+H+CPML+inject)",
+        "value": round(value, 2),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "768x768x256 (z fitted to 255) Yee grid, dx=lambda/24, "
+                               "theta=20deg, order-2 Bessel antenna R=320dx, 16-cell CPML",
+                   "cells": cells, "tile_rows": info.tile_rows,
+                   "tile_zchunk": info.tile_zchunk},
+        "step_hbm_fraction": round(step_gbs / HBM_PEAK_GBS, 4),
+        "kernels_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()},
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -130,6 +130,8 @@ typedef struct fdtd_info {
     int32_t tile_zchunk;         /* fused kernel: planes per wavefront        */
     int64_t step;                /* completed steps                           */
     int64_t device_bytes;        /* device memory held by the context         */
+    int64_t interior_cells;      /* cells per step updated by the fused        */
+                                 /* interior kernel (rest: edge kernel)        */
 } fdtd_info;
 
 /* Library version string (static storage). */
@@ -220,6 +222,22 @@ int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
  * keep the fastest. *best_rows / *best_zchunk may be NULL. */
 int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,
                   int32_t *best_zchunk);
+
+/* ---- kernel timing --------------------------------------------------------
+ * With profiling on, every kernel the context launches is bracketed by HIP
+ * events on its stream; fdtd_profile_read synchronises and returns, per
+ * kernel name, the number of launches and their summed duration (ms). */
+typedef struct fdtd_kernel_profile {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} fdtd_kernel_profile;
+
+/* Turn per-launch timing on (1) or off (0); either way the counters reset. */
+int fdtd_profile_enable(fdtd_ctx *ctx, int32_t on);
+
+/* Copy up to max entries; *count receives the number of kernel names. */
+int fdtd_profile_read(fdtd_ctx *ctx, fdtd_kernel_profile *out, int32_t max, int32_t *count);
 
 #ifdef __cplusplus
 }

@@ -47,7 +47,12 @@ class Info(ctypes.Structure):
                 ("n_source", ctypes.c_int32 * 6), ("n_slots", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_zchunk", ctypes.c_int32), ("step", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("interior_cells", ctypes.c_int64)]
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
 
 
 _CTX = ctypes.c_void_p
@@ -75,6 +80,9 @@ _SIGS = {
     "fdtd_set_tile": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]),
+    "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
+    "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None

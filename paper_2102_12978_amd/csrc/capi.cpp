@@ -14,9 +14,61 @@
 
 using namespace bfdtd;
 
-namespace bfdtd {
-int split_partial_count(const Problem& p);
-}
+
+// Event-pair timer for fdtd_profile_*: one event before each launch, the
+// next mark closes it.
+struct EventTimer : LaunchTimer {
+    hipStream_t stream = nullptr;
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> open_;
+    std::vector<std::pair<std::string, std::pair<long long, double>>> totals;
+    int pending = -1;
+    void mark(const char* name) override {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, stream);
+        if (pending >= 0) open_[pending].b = e;
+        pending = -1;
+        if (name) {
+            open_.push_back(Rec{name, e, nullptr});
+            pending = (int)open_.size() - 1;
+        } else if (open_.empty() || open_.back().b != e) {
+            (void)hipEventDestroy(e);
+        }
+    }
+    void collect() {
+        std::vector<hipEvent_t> seen;
+        for (auto& r : open_) {
+            if (!r.b) continue;
+            (void)hipEventSynchronize(r.b);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, r.a, r.b);
+            bool found = false;
+            for (auto& t : totals)
+                if (t.first == r.name) {
+                    t.second.first += 1;
+                    t.second.second += ms;
+                    found = true;
+                }
+            if (!found) totals.push_back({r.name, {1, (double)ms}});
+        }
+        for (auto& r : open_) {
+            for (hipEvent_t e : {r.a, r.b}) {
+                if (!e) continue;
+                if (std::find(seen.begin(), seen.end(), e) == seen.end()) {
+                    seen.push_back(e);
+                    (void)hipEventDestroy(e);
+                }
+            }
+        }
+        open_.clear();
+        pending = -1;
+    }
+    ~EventTimer() override { collect(); }
+};
 
 struct fdtd_ctx {
     fdtd_grid g{};
@@ -50,6 +102,7 @@ struct fdtd_ctx {
     int parity = 0;
     int kernel = FDTD_KERNEL_FUSED;
     int rows = 8, zchunk = 0;
+    EventTimer* timer = nullptr;
     std::string err;
 };
 
@@ -154,17 +207,41 @@ void ensure_time_tables(fdtd_ctx* c, long long upto) {
     c->p.tH = c->tH;
 }
 
+Frame step_frame(const fdtd_ctx* c) {
+    if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0};
+    return fused_interior_rect(c->p, c->rows);
+}
+
+int interior_partials(const fdtd_ctx* c) {
+    return c->kernel == FDTD_KERNEL_SPLIT ? 0 : fused_interior_tiles(c->p, c->rows, c->zchunk);
+}
+
 int partial_count(const fdtd_ctx* c) {
-    if (c->kernel == FDTD_KERNEL_SPLIT) return split_partial_count(c->p);
-    return fused_wave_count(c->p, c->rows, c->zchunk);
+    return interior_partials(c) + split_partial_count(c->p, step_frame(c));
 }
 
 void ensure_partials(fdtd_ctx* c) {
-    int need_n = std::max(partial_count(c), split_partial_count(c->p));
+    int need_n = std::max(1, partial_count(c));
     if (need_n <= c->epart_cap) return;
+    check(hipStreamSynchronize(c->stream), "sync");
     dfree(c, c->epart);
     c->epart = dalloc<double>(c, need_n);
     c->epart_cap = need_n;
+}
+
+// One leapfrog step: fused interior kernel, then the split kernels on the
+// frame (whole grid for FDTD_KERNEL_SPLIT).
+hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, int parity,
+                       double* epart) {
+    int ni = 0;
+    if (c->kernel != FDTD_KERNEL_SPLIT) {
+        hipError_t e = launch_fused_interior(q, n, parity, c->rows, c->zchunk, epart, c->stream,
+                                             c->timer);
+        if (e != hipSuccess) return e;
+        ni = interior_partials(c);
+    }
+    return launch_split_frame(q, n, parity, step_frame(c), epart ? epart + ni : nullptr,
+                              c->stream, c->timer);
 }
 
 void launch_one(fdtd_ctx* c, long long n) {
@@ -172,21 +249,20 @@ void launch_one(fdtd_ctx* c, long long n) {
     const bool in_window = c->plane >= 0 && n >= c->wbegin;
     q.diag_mask = in_window ? (int)(c->mask & 7u) : 0;
     q.plane = c->plane;
-    q.epart = (c->mask & FDTD_DIAG_ENERGY) ? c->epart : nullptr;
-    hipError_t e;
-    if (c->kernel == FDTD_KERNEL_SPLIT)
-        e = launch_split_step(q, n, c->parity, c->stream);
-    else
-        e = launch_fused_step(q, n, c->parity, c->rows, c->zchunk, c->stream);
-    check(e, "step launch");
-    if (q.epart) {
+    double* ep = (c->mask & FDTD_DIAG_ENERGY) ? c->epart : nullptr;
+    check(launch_step(c, q, n, c->parity, ep), "step launch");
+    if (ep) {
+        if (c->timer) c->timer->mark("energy_reduce");
         check(launch_energy_reduce(c->epart, partial_count(c), c->energy_dev, c->stream),
               "energy reduce");
+        if (c->timer) c->timer->mark(nullptr);
         c->energy_valid = true;
     }
     if (q.diag_mask) c->count += 1;
     c->parity ^= 1;
     c->step += 1;
+    // bound the number of outstanding timing events
+    if (c->timer && c->timer->open_.size() > 4096) c->timer->collect();
 }
 
 }  // namespace
@@ -291,6 +367,7 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
 int fdtd_destroy(fdtd_ctx* ctx) {
     if (!ctx) return FDTD_OK;
     if (!ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
+    delete ctx->timer;
     for (void* ptr : ctx->allocs) (void)hipFree(ptr);
     delete ctx;
     return FDTD_OK;
@@ -536,6 +613,8 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->tile_zchunk = c->zchunk;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
+    const Frame fr = step_frame(c);
+    out->interior_cells = (long long)(fr.x1 - fr.x0) * (fr.y1 - fr.y0) * c->p.nz;
     return FDTD_OK;
 }
 
@@ -579,7 +658,6 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         // the next real step overwrites: the state is left as it was.
         Problem q = c->p;
         q.diag_mask = 0;
-        q.epart = nullptr;
         q.rec = nullptr;
         const int nz = c->p.nz;
         std::vector<int> chunks = {0};
@@ -590,12 +668,17 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         check(hipEventCreate(&e1), "event");
         float best = 1e30f;
         int br = c->rows, bz = c->zchunk;
+        const int keep_rows = c->rows, keep_z = c->zchunk;
+        LaunchTimer* keep_timer = c->timer;
+        c->timer = nullptr;
         for (int rows : {4, 8}) {
             for (int cz : chunks) {
-                check(launch_fused_step(q, c->step, c->parity, rows, cz, c->stream), "trial");
+                c->rows = rows;
+                c->zchunk = cz;
+                check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
                 check(hipEventRecord(e0, c->stream), "event");
                 for (int s = 0; s < steps_per_trial; ++s)
-                    check(launch_fused_step(q, c->step, c->parity, rows, cz, c->stream), "trial");
+                    check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
                 check(hipEventRecord(e1, c->stream), "event");
                 check(hipEventSynchronize(e1), "event");
                 float ms = 0.f;
@@ -607,6 +690,9 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                 }
             }
         }
+        c->rows = keep_rows;
+        c->zchunk = keep_z;
+        c->timer = static_cast<EventTimer*>(keep_timer);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         c->rows = br;
@@ -614,6 +700,36 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         ensure_partials(c);
         if (best_rows) *best_rows = br;
         if (best_zchunk) *best_zchunk = bz;
+    });
+}
+
+int fdtd_profile_enable(fdtd_ctx* c, int32_t on) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        check(hipStreamSynchronize(c->stream), "sync");
+        delete c->timer;
+        c->timer = nullptr;
+        if (on) {
+            c->timer = new EventTimer();
+            c->timer->stream = c->stream;
+        }
+    });
+}
+
+int fdtd_profile_read(fdtd_ctx* c, fdtd_kernel_profile* out, int32_t max, int32_t* count) {
+    if (!c || !count || max < 0 || (max > 0 && !out)) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(c->timer != nullptr, "profiling is off", FDTD_ESTATE);
+        check(hipStreamSynchronize(c->stream), "sync");
+        c->timer->collect();
+        const auto& t = c->timer->totals;
+        *count = (int32_t)t.size();
+        for (int32_t i = 0; i < max && i < (int32_t)t.size(); ++i) {
+            std::memset(out[i].name, 0, sizeof out[i].name);
+            std::strncpy(out[i].name, t[i].first.c_str(), sizeof out[i].name - 1);
+            out[i].launches = t[i].second.first;
+            out[i].total_ms = t[i].second.second;
+        }
     });
 }
 

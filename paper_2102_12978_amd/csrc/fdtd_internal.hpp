@@ -43,7 +43,6 @@ struct Problem {
     const float2* tE;               // [step] f(t_{n+1}) e^{-iω(t_{n+1}-T0)}
     const float2* tH;               // [step] f(t_{n+3/2}) e^{-iω(t_{n+3/2}-T0)}
     double* fl;                     // [3][ny][nx] plane sums (E_x², E_y², E_z²)
-    double* epart;                  // energy partial sums, one per wavefront
     float* rec;                     // E_y plane record (adjoint), or null
     long long rec_begin;            // first recorded step
 };
@@ -103,11 +102,32 @@ void cpml_axis_tables(int n, int npml, double delta_ratio, const fdtd_grid& g, d
 
 std::string validate_grid(const fdtd_grid& g);
 
-// Kernel launchers (kernels_*.hip)
-hipError_t launch_split_step(const Problem& p, long long n, int parity, hipStream_t s);
-hipError_t launch_fused_step(const Problem& p, long long n, int parity, int rows, int zchunk,
-                             hipStream_t s);
-int fused_wave_count(const Problem& p, int rows, int zchunk);
+// Optional per-launch timing: launchers call mark(name) before each kernel
+// and mark(nullptr) after the last one.
+struct LaunchTimer {
+    virtual void mark(const char* name) = 0;
+    virtual ~LaunchTimer() {}
+};
+
+// Interior rectangle of cells [x0, x1) × [y0, y1) handled by the fused
+// kernel; the rest of the grid (the frame) goes through the split kernels.
+// All zero: no interior, the whole grid is frame.
+struct Frame {
+    int x0, x1, y0, y1;
+};
+
+// Fused interior kernel (kernels_fused.hip)
+Frame fused_interior_rect(const Problem& p, int rows);
+int fused_interior_tiles(const Problem& p, int rows, int zchunk);
+hipError_t launch_fused_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
+                                 double* epart, hipStream_t s, LaunchTimer* timer);
+
+// Split kernels over the frame (kernels_split.hip)
+long long frame_columns(const Problem& p, const Frame& fr);
+int split_partial_count(const Problem& p, const Frame& fr);
+hipError_t launch_split_frame(const Problem& p, long long n, int parity, const Frame& fr,
+                              double* epart, hipStream_t s, LaunchTimer* timer);
+
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 
 }  // namespace bfdtd

@@ -1,7 +1,13 @@
 // Two-kernel Yee step (one thread per cell): E update + E source, then
 // H update + H source, each reading the old ping-pong buffer and writing the
-// new one. The plain form of the step; it moves 72 B per cell-update and
-// serves as the cross-check of the fused kernel.
+// new one. It carries every boundary case (PEC walls, CPML slabs, periodic
+// wrap) and moves 72 B per cell-update.
+//
+// It runs either on the whole grid (FDTD_KERNEL_SPLIT) or on the frame of
+// cells around the interior rectangle that the fused kernel handles; the
+// frame is enumerated as a flat list of (x, y) columns: the bottom rows
+// y < y0, the top rows y >= y1, then the left (x < x0) and right (x >= x1)
+// strips of the rows in between.
 #include <hip/hip_runtime.h>
 
 #include "kernels_common.hpp"
@@ -10,27 +16,48 @@ namespace bfdtd {
 
 namespace {
 
-constexpr int BX = 64, BY = 4;
+constexpr int BT = 256;
 
 __device__ __forceinline__ void block_energy(double v, double* out) {
-    __shared__ double red[BX * BY / 64];
+    __shared__ double red[BT / 64];
     v = wave_sum(v);
-    int tid = threadIdx.y * BX + threadIdx.x;
+    const int tid = threadIdx.x;
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
-    if (tid == 0) {
-        double s = 0.0;
-        for (int w = 0; w < BX * BY / 64; ++w) s += red[w];
-        *out = s;
-    }
+    if (tid == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void __launch_bounds__(BX * BY)
-split_e_kernel(Problem p, long long n, int par) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    const bool inside = i < p.nx && j < p.ny;
+__device__ __forceinline__ bool frame_column(const Frame& fr, int nx, int ny, long long c, int* x,
+                                             int* y) {
+    const long long nb = (long long)fr.y0 * nx;
+    const long long nt = (long long)(ny - fr.y1) * nx;
+    const long long nl = (long long)(fr.y1 - fr.y0) * fr.x0;
+    const long long nr = (long long)(fr.y1 - fr.y0) * (nx - fr.x1);
+    if (c < nb) {
+        *y = (int)(c / nx);
+        *x = (int)(c % nx);
+    } else if ((c -= nb) < nt) {
+        *y = fr.y1 + (int)(c / nx);
+        *x = (int)(c % nx);
+    } else if ((c -= nt) < nl) {
+        *y = fr.y0 + (int)(c / fr.x0);
+        *x = (int)(c % fr.x0);
+    } else if ((c -= nl) < nr) {
+        const int wdt = nx - fr.x1;
+        *y = fr.y0 + (int)(c / wdt);
+        *x = fr.x1 + (int)(c % wdt);
+    } else {
+        return false;
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(BT)
+split_e_kernel(Problem p, long long n, int par, Frame fr, long long ncols, double* epart) {
+    int i = 0, j = 0;
+    const int k = blockIdx.y;
+    const long long col = (long long)blockIdx.x * BT + threadIdx.x;
+    const bool inside = col < ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
     double e2 = 0.0;
     if (inside) {
         auto fo = [&](int c) -> const float* { return fptr(p, par, c); };
@@ -78,12 +105,8 @@ split_e_kernel(Problem p, long long n, int par) {
             const float b = cy_tab(p, T_EB)[j], c = cy_tab(p, T_EC)[j], kinv = cy_tab(p, T_EK)[j];
             const size_t q = psiy_at(p, k, ys, i);
             float px = pptr(p, par, P_EXY)[q], pz = pptr(p, par, P_EZY)[q];
-            if (!hold_y) {
-                px = b * px + c * d_yhz;
-            }
-            if (!hold_y && !hold_x) {
-                pz = b * pz + c * d_yhx;
-            }
+            if (!hold_y) px = b * px + c * d_yhz;
+            if (!hold_y && !hold_x) pz = b * pz + c * d_yhx;
             pptr(p, par ^ 1, P_EXY)[q] = px;
             pptr(p, par ^ 1, P_EZY)[q] = pz;
             ty_hz = kinv * d_yhz + px;
@@ -106,32 +129,28 @@ split_e_kernel(Problem p, long long n, int par) {
         fn(EX)[id] = ex;
         fn(EY)[id] = ey;
         fn(EZ)[id] = ez;
-        if (k == p.plane && p.diag_mask) {
+        if (k == p.plane) {
             const size_t pl = (size_t)j * p.nx + i, ps = (size_t)p.nx * p.ny;
             if (p.diag_mask & FDTD_DIAG_EX2) p.fl[pl] += (double)ex * ex;
             if (p.diag_mask & FDTD_DIAG_EY2) p.fl[ps + pl] += (double)ey * ey;
             if (p.diag_mask & FDTD_DIAG_EZ2) p.fl[2 * ps + pl] += (double)ez * ez;
+            if (p.rec) p.rec[(size_t)(n - p.rec_begin) * ps + pl] = ey;
         }
-        if (p.rec && k == p.plane) p.rec[(size_t)(n - p.rec_begin) * p.nx * p.ny +
-                                         (size_t)j * p.nx + i] = ey;
         e2 = (double)ex * ex + (double)ey * ey + (double)ez * ez;
     }
-    if (p.epart) {
-        const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        block_energy(e2, p.epart + b);
-    }
+    if (epart) block_energy(e2, epart + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
-__global__ void __launch_bounds__(BX * BY)
-split_h_kernel(Problem p, long long n, int par) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    const bool inside = i < p.nx && j < p.ny;
+__global__ void __launch_bounds__(BT)
+split_h_kernel(Problem p, long long n, int par, Frame fr, long long ncols, double* epart) {
+    int i = 0, j = 0;
+    const int k = blockIdx.y;
+    const long long col = (long long)blockIdx.x * BT + threadIdx.x;
+    const bool inside = col < ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
     double hh = 0.0;
     if (inside) {
         auto fo = [&](int c) -> const float* { return fptr(p, par, c); };
-        auto fn = [&](int c) -> float* { return fptr(p, par ^ 1, c); };   // E^{n+1} already written here
+        auto fn = [&](int c) -> float* { return fptr(p, par ^ 1, c); };  // E^{n+1} is here
         const bool per = p.periodic != 0;
         const int kp = k + 1 == p.nz ? 0 : k + 1;
         int ip = i + 1, jp = j + 1;
@@ -196,27 +215,36 @@ split_h_kernel(Problem p, long long n, int par) {
         fn(HZ)[id] = hz;
         hh = (double)hx0 * hx + (double)hy0 * hy + (double)hz0 * hz;
     }
-    if (p.epart) {
-        const size_t nb = (size_t)gridDim.x * gridDim.y * gridDim.z;
-        const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        block_energy(hh, p.epart + nb + b);
-    }
+    if (epart) block_energy(hh, epart + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 }  // namespace
 
-hipError_t launch_split_step(const Problem& p, long long n, int parity, hipStream_t s) {
-    dim3 block(BX, BY, 1);
-    dim3 grid((p.nx + BX - 1) / BX, (p.ny + BY - 1) / BY, p.nz);
-    hipLaunchKernelGGL(split_e_kernel, grid, block, 0, s, p, n, parity);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(split_h_kernel, grid, block, 0, s, p, n, parity);
-    return hipGetLastError();
+long long frame_columns(const Problem& p, const Frame& fr) {
+    return (long long)fr.y0 * p.nx + (long long)(p.ny - fr.y1) * p.nx +
+           (long long)(fr.y1 - fr.y0) * (fr.x0 + p.nx - fr.x1);
 }
 
-int split_partial_count(const Problem& p) {
-    return 2 * ((p.nx + BX - 1) / BX) * ((p.ny + BY - 1) / BY) * p.nz;
+int split_partial_count(const Problem& p, const Frame& fr) {
+    const long long nc = frame_columns(p, fr);
+    return nc == 0 ? 0 : 2 * (int)((nc + BT - 1) / BT) * p.nz;
+}
+
+hipError_t launch_split_frame(const Problem& p, long long n, int parity, const Frame& fr,
+                              double* epart, hipStream_t s, LaunchTimer* timer) {
+    const long long nc = frame_columns(p, fr);
+    if (nc == 0) return hipSuccess;
+    dim3 grid((unsigned)((nc + BT - 1) / BT), p.nz, 1);
+    const size_t nb = (size_t)grid.x * grid.y;
+    if (timer) timer->mark(fr.x1 > 0 ? "frame_e" : "split_e");
+    hipLaunchKernelGGL(split_e_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, epart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (timer) timer->mark(fr.x1 > 0 ? "frame_h" : "split_h");
+    hipLaunchKernelGGL(split_h_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc,
+                       epart ? epart + nb : nullptr);
+    if (timer) timer->mark(nullptr);
+    return hipGetLastError();
 }
 
 }  // namespace bfdtd

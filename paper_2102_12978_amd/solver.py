@@ -176,6 +176,16 @@ class Solver:
     def set_tile(self, rows, zchunk=0):
         self._c(self._lib.fdtd_set_tile(self._ctx, rows, zchunk))
 
+    def profile(self, on=True):
+        self._c(self._lib.fdtd_profile_enable(self._ctx, 1 if on else 0))
+
+    def profile_read(self):
+        arr = (L.KernelProfile * 16)()
+        n = ctypes.c_int32()
+        self._c(self._lib.fdtd_profile_read(self._ctx, arr, 16, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms)
+                for i in range(min(n.value, 16))}
+
     def autotune(self, steps_per_trial=5):
         r = ctypes.c_int32()
         z = ctypes.c_int32()
