@@ -3,7 +3,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "lib", "libbesselfdtd.so")
+LIB_PATH = os.environ.get("BESSELFDTD_LIB") or os.path.join(HERE, "lib", "libbesselfdtd.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "fdtd.h")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5

@@ -101,7 +101,7 @@ struct fdtd_ctx {
     long long step = 0;
     int parity = 0;
     int kernel = FDTD_KERNEL_FUSED;
-    int rows = 8, zchunk = 0;
+    int rows = 4, zchunk = 0;
     EventTimer* timer = nullptr;
     std::string err;
 };
@@ -207,8 +207,11 @@ void ensure_time_tables(fdtd_ctx* c, long long upto) {
     c->p.tH = c->tH;
 }
 
-Frame step_frame(const fdtd_ctx* c) {
-    if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0};
+// A fused step: the interior kernel, then the split kernels on the frame
+// around it (the whole grid when there is no interior or for the split
+// kernel choice).
+Frame interior_of(const fdtd_ctx* c) {
+    if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0, 0};
     return fused_interior_rect(c->p, c->rows);
 }
 
@@ -217,7 +220,7 @@ int interior_partials(const fdtd_ctx* c) {
 }
 
 int partial_count(const fdtd_ctx* c) {
-    return interior_partials(c) + split_partial_count(c->p, step_frame(c));
+    return interior_partials(c) + split_partial_count(c->p, interior_of(c));
 }
 
 void ensure_partials(fdtd_ctx* c) {
@@ -229,19 +232,18 @@ void ensure_partials(fdtd_ctx* c) {
     c->epart_cap = need_n;
 }
 
-// One leapfrog step: fused interior kernel, then the split kernels on the
-// frame (whole grid for FDTD_KERNEL_SPLIT).
 hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, int parity,
                        double* epart) {
-    int ni = 0;
-    if (c->kernel != FDTD_KERNEL_SPLIT) {
+    const Frame fr = interior_of(c);
+    int off = 0;
+    if (fr.x1 > fr.x0) {
         hipError_t e = launch_fused_interior(q, n, parity, c->rows, c->zchunk, epart, c->stream,
                                              c->timer);
         if (e != hipSuccess) return e;
-        ni = interior_partials(c);
+        off = interior_partials(c);
     }
-    return launch_split_frame(q, n, parity, step_frame(c), epart ? epart + ni : nullptr,
-                              c->stream, c->timer);
+    return launch_split_frame(q, n, parity, fr, epart ? epart + off : nullptr, c->stream,
+                              c->timer);
 }
 
 void launch_one(fdtd_ctx* c, long long n) {
@@ -613,7 +615,7 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->tile_zchunk = c->zchunk;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
-    const Frame fr = step_frame(c);
+    const Frame fr = interior_of(c);
     out->interior_cells = (long long)(fr.x1 - fr.x0) * (fr.y1 - fr.y0) * c->p.nz;
     return FDTD_OK;
 }

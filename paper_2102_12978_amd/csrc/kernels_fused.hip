@@ -6,22 +6,23 @@
 // the split kernels (kernels_split.hip), which carry every boundary case.
 //
 // Work decomposition (CDNA4, wave64). Every wavefront is independent (no LDS,
-// no barriers): it owns a block of 62 x cells × TY y rows and marches along z
-// over a chunk of planes, keeping two planes of each field in registers.
-//   * x: lane l sits at x = 62·seg - 1 + l. Lanes 1..62 own their cell;
-//     lane 0 supplies H at x-1 to lane 1, lane 63 supplies E_new at x+1 to
-//     lane 62 (it recomputes E there). x neighbours move between lanes with
-//     cross-lane shuffles.
+// no barriers): it owns a block of 64 x cells (one 256-byte aligned row
+// segment, so every load and store is two whole 128-byte lines) × TY y rows
+// and marches along z over a chunk of planes, keeping two planes of each
+// field in registers.
+//   * x: lane l holds x = x0 + l; x neighbours move between lanes with
+//     cross-lane shuffles. Lane 0 fetches H at x0-1 with single-lane loads;
+//     lane 63 forms E_new(E_y, E_z) at x0+64 from single-lane loads, the
+//     value its H update needs.
 //   * y: each lane holds rows j0-1 .. j0+TY of H and j0 .. j0+TY of E in
 //     registers; E_new of row j0+TY is recomputed for the H update of the
 //     last owned row.
 //   * z: E_new(k+1) is formed from H_old(k+1) and H_old(k), then H_new(k)
 //     from E_new(k) and E_new(k+1); the z index wraps (periodic axis).
 // Addresses are a uniform component base (scalar registers) plus a 32-bit
-// per-lane byte offset, so a load needs one vector register for its address.
-// Consecutive workgroups are spread over the 8 XCDs by the hardware; the
-// block index is remapped so each XCD receives a contiguous run of tiles and
-// the y-halo rows shared by neighbouring tiles stay in one L2.
+// per-lane byte offset. Hardware block b runs on XCD b % 8; the block index
+// is remapped so each XCD receives a contiguous run of tiles and the y-halo
+// rows shared by neighbouring tiles stay in one L2.
 #include <hip/hip_runtime.h>
 
 #include "kernels_common.hpp"
@@ -31,7 +32,7 @@ namespace bfdtd {
 namespace {
 
 constexpr int WAVES_PER_BLOCK = 4;
-constexpr int SEG = 62;   // owned x cells per wavefront
+constexpr int SEG = 64;   // x cells per wavefront
 
 __device__ __forceinline__ float ldo(const float* base, unsigned boff) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
@@ -44,17 +45,15 @@ __device__ __forceinline__ void sto(float* base, unsigned boff, float v) {
 template <int TY>
 struct Tile {
     const Problem& p;
-    int x, j0;
-    bool own_x;
+    int x, j0, lane;
     unsigned ro[TY + 2];   // byte offset of (row j0 + r, x) in a plane, r = -1..TY
     unsigned pstride;      // bytes per plane
     const float* fo[6];    // component bases, old parity
     float* fw[6];          // component bases, new parity
 
     __device__ Tile(const Problem& pp, int par, int seg, int jj0) : p(pp), j0(jj0) {
-        const int lane = threadIdx.x & 63;
-        x = SEG * seg - 1 + lane;
-        own_x = lane >= 1 && lane <= SEG;
+        lane = threadIdx.x & 63;
+        x = SEG * seg + lane;
 #pragma unroll
         for (int r = -1; r <= TY; ++r) ro[r + 1] = 4u * (unsigned)((j0 + r) * p.pitch + x);
         pstride = 4u * (unsigned)(p.ny * p.pitch);
@@ -67,15 +66,23 @@ struct Tile {
     __device__ float ld(int c, int kk, int r) const {
         return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1]);
     }
+    // column x0 - 1 (used by lane 0) and column x0 + 64 (used by lane 63)
+    __device__ float ld_left(int c, int kk, int r) const {
+        return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1] - 4u * (unsigned)(lane + 1));
+    }
+    __device__ float ld_right(int c, int kk, int r) const {
+        return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1] + 4u * (unsigned)(SEG - lane));
+    }
     __device__ void st(int c, int kk, int r, float v) const {
         sto(fw[c], (unsigned)kk * pstride + ro[r + 1], v);
     }
 };
 
 // E_new on plane kk, rows 0..TY (ex/ey/ez hold E_old on entry); hx/hy/hz are
-// H_old(kk) (rows -1..TY, 0..TY, -1..TY), hxm/hym H_old(kk-1).
+// H_old(kk) (rows -1..TY, 0..TY, -1..TY), hxm/hym H_old(kk-1). Lane 0 takes
+// H at x0-1 from the column loads.
 template <int TY>
-__device__ __forceinline__ void e_plane(const Problem& p, long long n, int kk,
+__device__ __forceinline__ void e_plane(const Problem& p, const Tile<TY>& T, long long n, int kk,
                                         const int (&slot)[TY + 1], const float (&hx)[TY + 2],
                                         const float (&hy)[TY + 1], const float (&hz)[TY + 2],
                                         const float (&hxm)[TY], const float (&hym)[TY + 1],
@@ -86,10 +93,22 @@ __device__ __forceinline__ void e_plane(const Problem& p, long long n, int kk,
         pt0 = cmul(p.zph[2 * kk], t);
         pt1 = cmul(p.zph[2 * kk + 1], t);
     }
+    float hzl[TY], hyl[TY + 1];
+    if (T.lane == 0) {
+#pragma unroll
+        for (int r = 0; r <= TY; ++r) {
+            hyl[r] = T.ld_left(HY, kk, r);
+            if (r < TY) hzl[r] = T.ld_left(HZ, kk, r);
+        }
+    }
 #pragma unroll
     for (int r = 0; r <= TY; ++r) {
-        const float hz_im = __shfl_up(hz[r + 1], 1, 64);
-        const float hy_im = __shfl_up(hy[r], 1, 64);
+        float hz_im = __shfl_up(hz[r + 1], 1, 64);
+        float hy_im = __shfl_up(hy[r], 1, 64);
+        if (T.lane == 0) {
+            hy_im = hyl[r];
+            if (r < TY) hz_im = hzl[r];
+        }
         // E_x += S_y Δ_y H_z - S_z Δ_z H_y
         ex[r] += p.sy * (hz[r + 1] - hz[r]) - p.sz * (hy[r] - hym[r]);
         // E_z += S_x Δ_x H_y - S_y Δ_y H_x
@@ -105,16 +124,58 @@ __device__ __forceinline__ void e_plane(const Problem& p, long long n, int kk,
     }
 }
 
+// Lane 63: E_new(E_y, E_z) of rows 0..TY-1 at x0+64 on plane kk (the same
+// update as e_plane, with H at x0+63 from the lane's own registers).
+// hxh_km: H_x(x0+64) of plane kk-1, replaced by that of plane kk.
+template <int TY>
+__device__ __forceinline__ void e_halo_right(const Problem& p, const Tile<TY>& T, long long n,
+                                             int kk, const int (&slot_h)[TY],
+                                             const float (&hy)[TY + 1], const float (&hz)[TY + 2],
+                                             float (&hxh_km)[TY], float (&ey_h)[TY],
+                                             float (&ez_h)[TY]) {
+    float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
+    if (p.colmap) {
+        const float2 t = p.tE[n];
+        pt0 = cmul(p.zph[2 * kk], t);
+        pt1 = cmul(p.zph[2 * kk + 1], t);
+    }
+    float hx_prev = T.ld_right(HX, kk, -1);
+#pragma unroll
+    for (int r = 0; r < TY; ++r) {
+        const float hxr = T.ld_right(HX, kk, r);
+        const float hyr = T.ld_right(HY, kk, r);
+        const float hzr = T.ld_right(HZ, kk, r);
+        float vy = T.ld_right(EY, kk, r);
+        float vz = T.ld_right(EZ, kk, r);
+        vy += p.sz * (hxr - hxh_km[r]) - p.sx * (hzr - hz[r + 1]);
+        vz += p.sx * (hyr - hy[r]) - p.sy * (hxr - hx_prev);
+        if (slot_h[r] >= 0) {
+            const float2* a = p.amp + (size_t)slot_h[r] * 6;
+            vy += cmul_re(a[EY], pt0);
+            vz += cmul_re(a[EZ], pt1);
+        }
+        ey_h[r] = vy;
+        ez_h[r] = vz;
+        hxh_km[r] = hxr;
+        hx_prev = hxr;
+    }
+}
+
 template <int TY>
 __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par, int seg, int j0,
                                           int kb, int ke, double* epart_slot) {
     const Tile<TY> T(p, par, seg, j0);
     const int nz = p.nz, nx = p.nx, ny = p.ny;
+    const bool right = T.lane == 63;
 
-    int slot[TY + 1];
+    int slot[TY + 1], slot_h[TY];
 #pragma unroll
     for (int r = 0; r <= TY; ++r)
         slot[r] = p.colmap ? p.colmap[(size_t)(j0 + r) * nx + T.x] : -1;
+#pragma unroll
+    for (int r = 0; r < TY; ++r)
+        slot_h[r] = (p.colmap && right) ? p.colmap[(size_t)(j0 + r) * nx + T.x + 1] : -1;
+    float hxh[TY], eyh[TY], ezh[TY];   // lane 63: H_x(k), E_new(k) at x0+64
 
     // ---- prologue: E_new(kb) ------------------------------------------
     float hcx[TY], hcy[TY + 1], hcz[TY];      // H_old(k), kept for the H update
@@ -137,7 +198,12 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
                 ecy[r] = T.ld(EY, kb, r);
             }
         }
-        e_plane<TY>(p, n, kb, slot, hx, hy, hz, hxm, hym, ecx, ecy, ecz);
+        e_plane<TY>(p, T, n, kb, slot, hx, hy, hz, hxm, hym, ecx, ecy, ecz);
+        if (right) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) hxh[r] = T.ld_right(HX, km, r);
+            e_halo_right<TY>(p, T, n, kb, slot_h, hy, hz, hxh, eyh, ezh);
+        }
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
             hcx[r] = hx[r + 1];
@@ -150,7 +216,6 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
     double en = 0.0;
     auto store_e = [&](int kk, const float (&ex)[TY + 1], const float (&ey)[TY],
                        const float (&ez)[TY + 1]) {
-        if (!T.own_x) return;
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
             T.st(EX, kk, r, ex[r]);
@@ -185,7 +250,9 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
             }
             if (r >= 0 && r < TY) eny[r] = T.ld(EY, kn, r);
         }
-        e_plane<TY>(p, n, kn, slot, hx, hy, hz, hcx, hcy, enx, eny, enz);
+        e_plane<TY>(p, T, n, kn, slot, hx, hy, hz, hcx, hcy, enx, eny, enz);
+        float eyh_n[TY], ezh_n[TY];
+        if (right) e_halo_right<TY>(p, T, n, kn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
 
         // ---- H_new(k) ---------------------------------------------------
         float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
@@ -195,8 +262,12 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
         }
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
-            const float ey_ip = __shfl_down(ecy[r], 1, 64);
-            const float ez_ip = __shfl_down(ecz[r], 1, 64);
+            float ey_ip = __shfl_down(ecy[r], 1, 64);
+            float ez_ip = __shfl_down(ecz[r], 1, 64);
+            if (right) {
+                ey_ip = eyh[r];
+                ez_ip = ezh[r];
+            }
             // H_x -= S_y Δ_y E_z - S_z Δ_z E_y
             float vx = hcx[r] - (p.sy * (ecz[r + 1] - ecz[r]) - p.sz * (eny[r] - ecy[r]));
             // H_y -= S_z Δ_z E_x - S_x Δ_x E_z
@@ -209,12 +280,10 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
                 vy += cmul_re(a[HY], qt1);
                 vz += cmul_re(a[HZ], qt0);
             }
-            if (T.own_x) {
-                T.st(HX, k, r, vx);
-                T.st(HY, k, r, vy);
-                T.st(HZ, k, r, vz);
-                if (epart_slot) en += (double)hcx[r] * vx + (double)hcy[r] * vy + (double)hcz[r] * vz;
-            }
+            T.st(HX, k, r, vx);
+            T.st(HY, k, r, vy);
+            T.st(HZ, k, r, vz);
+            if (epart_slot) en += (double)hcx[r] * vx + (double)hcy[r] * vy + (double)hcz[r] * vz;
         }
         if (k + 1 < ke) store_e(kn, enx, eny, enz);
         // ---- rotate -----------------------------------------------------
@@ -231,17 +300,25 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
             ecx[r] = enx[r];
             ecz[r] = enz[r];
         }
+        if (right) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                eyh[r] = eyh_n[r];
+                ezh[r] = ezh_n[r];
+            }
+        }
     }
     if (epart_slot) {
         en = wave_sum(en);
-        if ((threadIdx.x & 63) == 0) *epart_slot = en;
+        if (T.lane == 0) *epart_slot = en;
     }
 }
 
 // Interior tiles: seg in [sx0, sx0 + nsx), sy in [sy0, sy0 + nsy), ncz z chunks.
 template <int TY>
 __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK)
-fused_interior_kernel(Problem p, long long n, int par, int sx0, int sy0, int nsx, int nsy,
+__attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 1))) fused_interior_kernel(
+    Problem p, long long n, int par, int sx0, int sy0, int nsx, int nsy,
                       int ncz, int cz, int nblocks_padded, double* epart) {
     // hardware block b runs on XCD b % 8; give each XCD a contiguous run
     const int b = blockIdx.x;
@@ -257,14 +334,14 @@ fused_interior_kernel(Problem p, long long n, int par, int sx0, int sy0, int nsx
 }
 
 // Interior tile rectangle [sx0, sx1) × [sy0, sy1) in tile units (may be empty):
-// every lane x = 62 seg - 1 .. 62 seg + 62 and every row j0 - 1 .. j0 + TY
-// lies in [max(npml, 1), n - npml - 1].
+// every lane x = 64 seg .. 64 seg + 63, the columns x0 - 1 and x0 + 64 and
+// every row j0 - 1 .. j0 + TY lie in [max(npml, 1), n - npml - 1].
 void interior_tiles(const Problem& p, int rows, int* sx0, int* sx1, int* sy0, int* sy1) {
     *sx0 = *sx1 = *sy0 = *sy1 = 0;
     if (p.periodic) return;
     const int m = p.npml > 0 ? p.npml : 1;
     const int a = (m + 1 + SEG - 1) / SEG;
-    const int b = (p.nx - p.npml - 1 - 62) >= 0 ? (p.nx - p.npml - 1 - 62) / SEG + 1 : 0;
+    const int b = (p.nx - p.npml - SEG - 1) >= 0 ? (p.nx - p.npml - SEG - 1) / SEG + 1 : 0;
     const int c = (m + 1 + rows - 1) / rows;
     const int d = (p.ny - p.npml - 1 - rows) >= 0 ? (p.ny - p.npml - 1 - rows) / rows + 1 : 0;
     if (a < b && c < d) {
@@ -273,7 +350,7 @@ void interior_tiles(const Problem& p, int rows, int* sx0, int* sx1, int* sy0, in
 }
 
 int zchunks(const Problem& p, int zchunk, int* cz) {
-    *cz = zchunk > 0 ? zchunk : p.nz;
+    *cz = zchunk > 0 ? min(zchunk, p.nz) : p.nz;
     return (p.nz + *cz - 1) / *cz;
 }
 
@@ -298,8 +375,9 @@ hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, do
 Frame fused_interior_rect(const Problem& p, int rows) {
     int sx0, sx1, sy0, sy1;
     interior_tiles(p, rows, &sx0, &sx1, &sy0, &sy1);
-    if (sx0 >= sx1) return Frame{0, 0, 0, 0};
-    return Frame{SEG * sx0, SEG * sx1, rows * sy0, rows * sy1};
+    if (sx0 >= sx1) return Frame{0, 0, 0, 0, 0};
+    // stride is 0: the rectangle is the region the split frame pass excludes
+    return Frame{SEG * sx0, SEG * sx1, rows * sy0, rows * sy1, 0};
 }
 
 int fused_interior_tiles(const Problem& p, int rows, int zchunk) {

@@ -1,0 +1,129 @@
+// Per-cell Yee updates with every boundary case (PEC walls, CPML slabs,
+// periodic test mode) and the antenna soft source. Shared by the split
+// kernels and the LDS-tiled fused kernel so both compute bit-identical
+// values for a cell.
+#pragma once
+
+#include "kernels_common.hpp"
+
+namespace bfdtd {
+
+// E update of cell (i, j, k) (paper §4 Yee scheme + CPML + soft source):
+//   E_x += S_y [Δ_y H_z]_cpml - S_z Δ_z H_y
+//   E_y += S_z Δ_z H_x - S_x [Δ_x H_z]_cpml
+//   E_z += S_x [Δ_x H_y]_cpml - S_y [Δ_y H_x]_cpml
+// with backward differences of H̃^{n+1/2}; [Δ]_cpml = Δ/κ + ψ, ψ ← b ψ + c Δ
+// (ψ of the old parity read, of the new parity written when store_psi).
+// E on the x = 0 / y = 0 PEC wall is held. pt0 / pt1: e^{iβz} T_E(n) at the
+// integer / half z planes of this k.
+struct HNbr {
+    float hx, hx_jm, hx_km;    // H_x at (i, j), (i, j-1), plane k-1
+    float hy, hy_im, hy_km;    // H_y at (i, j), (i-1, j), plane k-1
+    float hz, hz_im, hz_jm;    // H_z at (i, j), (i-1, j), (i, j-1)
+};
+
+// BND = false compiles the wall and CPML handling out (cells known to be
+// away from both).
+template <bool BND = true>
+__device__ __forceinline__ void e_cell(const Problem& p, int par, int i, int j, int k,
+                                       const HNbr& h, float& ex, float& ey, float& ez, int slot,
+                                       float2 pt0, float2 pt1, bool store_psi) {
+    const bool per = p.periodic != 0;
+    const float d_yhz = h.hz - h.hz_jm, d_zhy = h.hy - h.hy_km;
+    const float d_zhx = h.hx - h.hx_km, d_xhz = h.hz - h.hz_im;
+    const float d_xhy = h.hy - h.hy_im, d_yhx = h.hx - h.hx_jm;
+    const bool hold_x = BND && !per && i == 0;   // E_y, E_z on the x = 0 wall
+    const bool hold_y = BND && !per && j == 0;   // E_x, E_z on the y = 0 wall
+    const int xs = BND ? slab_index(i, p.nx, p.npml) : -1;
+    const int ys = BND ? slab_index(j, p.ny, p.npml) : -1;
+    float tx_hz = d_xhz, tx_hy = d_xhy, ty_hz = d_yhz, ty_hx = d_yhx;
+    if (xs >= 0) {
+        const float b = cx_tab(p, T_EB)[i], c = cx_tab(p, T_EC)[i], kinv = cx_tab(p, T_EK)[i];
+        const size_t q = psix_at(p, k, j, xs);
+        float py = pptr(p, par, P_EYX)[q], pz = pptr(p, par, P_EZX)[q];
+        if (!hold_x) py = b * py + c * d_xhz;
+        if (!hold_x && !hold_y) pz = b * pz + c * d_xhy;
+        if (store_psi) {
+            pptr(p, par ^ 1, P_EYX)[q] = py;
+            pptr(p, par ^ 1, P_EZX)[q] = pz;
+        }
+        tx_hz = kinv * d_xhz + py;
+        tx_hy = kinv * d_xhy + pz;
+    }
+    if (ys >= 0) {
+        const float b = cy_tab(p, T_EB)[j], c = cy_tab(p, T_EC)[j], kinv = cy_tab(p, T_EK)[j];
+        const size_t q = psiy_at(p, k, ys, i);
+        float px = pptr(p, par, P_EXY)[q], pz = pptr(p, par, P_EZY)[q];
+        if (!hold_y) px = b * px + c * d_yhz;
+        if (!hold_y && !hold_x) pz = b * pz + c * d_yhx;
+        if (store_psi) {
+            pptr(p, par ^ 1, P_EXY)[q] = px;
+            pptr(p, par ^ 1, P_EZY)[q] = pz;
+        }
+        ty_hz = kinv * d_yhz + px;
+        ty_hx = kinv * d_yhx + pz;
+    }
+    if (!hold_y) ex += p.sy * ty_hz - p.sz * d_zhy;
+    if (!hold_x) ey += p.sz * d_zhx - p.sx * tx_hz;
+    if (!hold_x && !hold_y) ez += p.sx * tx_hy - p.sy * ty_hx;
+    if (slot >= 0) {
+        const float2* a = p.amp + (size_t)slot * 6;
+        ex += cmul_re(a[EX], pt0);
+        ey += cmul_re(a[EY], pt0);
+        ez += cmul_re(a[EZ], pt1);
+    }
+}
+
+// H update of cell (i, j, k):
+//   H_x -= S_y [Δ_y E_z]_cpml - S_z Δ_z E_y
+//   H_y -= S_z Δ_z E_x - S_x [Δ_x E_z]_cpml
+//   H_z -= S_x [Δ_x E_y]_cpml - S_y [Δ_y E_x]_cpml
+// with forward differences of E^{n+1}; qt0 / qt1: e^{iβz} T_H(n).
+struct ENbr {
+    float ex, ex_jp, ex_kp;    // E_x at (i, j), (i, j+1), plane k+1
+    float ey, ey_ip, ey_kp;    // E_y at (i, j), (i+1, j), plane k+1
+    float ez, ez_ip, ez_jp;    // E_z at (i, j), (i+1, j), (i, j+1)
+};
+
+template <bool BND = true>
+__device__ __forceinline__ void h_cell(const Problem& p, int par, int i, int j, int k,
+                                       const ENbr& e, float& hx, float& hy, float& hz, int slot,
+                                       float2 qt0, float2 qt1) {
+    const float d_yez = e.ez_jp - e.ez, d_zey = e.ey_kp - e.ey;
+    const float d_zex = e.ex_kp - e.ex, d_xez = e.ez_ip - e.ez;
+    const float d_xey = e.ey_ip - e.ey, d_yex = e.ex_jp - e.ex;
+    const int xs = BND ? slab_index(i, p.nx, p.npml) : -1;
+    const int ys = BND ? slab_index(j, p.ny, p.npml) : -1;
+    float tx_ez = d_xez, tx_ey = d_xey, ty_ez = d_yez, ty_ex = d_yex;
+    if (xs >= 0) {
+        const float b = cx_tab(p, T_HB)[i], c = cx_tab(p, T_HC)[i], kinv = cx_tab(p, T_HK)[i];
+        const size_t q = psix_at(p, k, j, xs);
+        const float py = b * pptr(p, par, P_HYX)[q] + c * d_xez;
+        const float pz = b * pptr(p, par, P_HZX)[q] + c * d_xey;
+        pptr(p, par ^ 1, P_HYX)[q] = py;
+        pptr(p, par ^ 1, P_HZX)[q] = pz;
+        tx_ez = kinv * d_xez + py;
+        tx_ey = kinv * d_xey + pz;
+    }
+    if (ys >= 0) {
+        const float b = cy_tab(p, T_HB)[j], c = cy_tab(p, T_HC)[j], kinv = cy_tab(p, T_HK)[j];
+        const size_t q = psiy_at(p, k, ys, i);
+        const float px = b * pptr(p, par, P_HXY)[q] + c * d_yez;
+        const float pz = b * pptr(p, par, P_HZY)[q] + c * d_yex;
+        pptr(p, par ^ 1, P_HXY)[q] = px;
+        pptr(p, par ^ 1, P_HZY)[q] = pz;
+        ty_ez = kinv * d_yez + px;
+        ty_ex = kinv * d_yex + pz;
+    }
+    hx -= p.sy * ty_ez - p.sz * d_zey;
+    hy -= p.sz * d_zex - p.sx * tx_ez;
+    hz -= p.sx * tx_ey - p.sy * ty_ex;
+    if (slot >= 0) {
+        const float2* a = p.amp + (size_t)slot * 6;
+        hx += cmul_re(a[HX], qt1);
+        hy += cmul_re(a[HY], qt1);
+        hz += cmul_re(a[HZ], qt0);
+    }
+}
+
+}  // namespace bfdtd

@@ -161,6 +161,14 @@ def random_state_vectors(shape_f, shapes_psi, seed):
     return f, p
 
 
+def parity_mid():
+    """Several fused-kernel segments plus a frame: 300×150×(24 hint), 10-cell
+    CPML, θ = 25°, m = 1, antenna of radius 60Δx crossing interior and frame,
+    40 steps."""
+    return Workload("p_300x150x24_theta25_m1", 300, 150, 24, 14.0, 25.0, 1, 60.0, 3.0, 10, 40,
+                    ramp_periods=2.0)
+
+
 def parity_small():
     """Several-tile case with ragged edges: 100×72×(40 hint), source in the
     interior, 16-cell CPML, θ = 18°, m = 1, 60 steps."""

@@ -50,11 +50,11 @@ def test_config0_forward(kernel):
     s.close()
 
 
-@pytest.mark.parametrize("rows,zchunk", [(4, 0), (8, 0), (4, 7), (8, 13)])
-def test_ragged_tiles_with_cpml_and_source(rows, zchunk):
-    """100×72 grid (ragged in x and y for every tile shape), z chunks that do
-    not divide nz, 10-cell CPML, order-1 source, 60 steps."""
-    w = W.parity_small()
+@pytest.mark.parametrize("rows,zchunk", [(4, 0), (8, 0), (4, 7), (8, 9)])
+def test_fused_interior_frame_and_fixup(rows, zchunk):
+    """300×150: three fused segments, ragged frame, z chunks that do not
+    divide nz, 10-cell CPML, an antenna crossing interior and frame."""
+    w = W.parity_mid()
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=rows, zchunk=zchunk)
     s.step(w.steps)
     g, st = GC.oracle_run(w, w.steps)
@@ -62,13 +62,15 @@ def test_ragged_tiles_with_cpml_and_source(rows, zchunk):
     s.close()
 
 
-def test_split_ragged():
+def test_ragged_small_grid():
+    """100×72: too small for an interior, all cells go through the frame."""
     w = W.parity_small()
-    s = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
-    s.step(w.steps)
-    g, st = GC.oracle_run(w, w.steps)
-    _compare(s, st, g)
-    s.close()
+    for kernel in (L.KERNEL_SPLIT, L.KERNEL_FUSED):
+        s = GC.gpu_solver(w, kernel=kernel)
+        s.step(w.steps)
+        g, st = GC.oracle_run(w, w.steps)
+        _compare(s, st, g)
+        s.close()
 
 
 @pytest.mark.parametrize("bc", [P.BC_PERIODIC, P.BC_PEC])
@@ -111,8 +113,7 @@ def test_random_start_no_source(bc, kernel):
 def test_random_start_with_source_and_cpml():
     """Random start (walls zeroed) plus the antenna and CPML: the general
     state including nonzero CPML memories from the first step."""
-    w = W.parity_small()
-    w.steps = 40
+    w = W.parity_mid()
     g, st0 = GC.random_start(w, P.BC_CPML, seed=4)
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
     for i, c in enumerate(GC.COMPS):
@@ -125,10 +126,9 @@ def test_random_start_with_source_and_cpml():
 
 def test_plane_diagnostics_and_energy():
     """⟨E_x²⟩, ⟨E_y²⟩, ⟨E_z²⟩ on the mid plane over a window, and W^n."""
-    w = W.parity_small()
-    w.steps = 50
+    w = W.parity_mid()
     g = cases.oracle_grid(w)
-    plane, wb = g.nz // 2, 30
+    plane, wb = g.nz // 2, 25
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=9)
     s.set_diagnostics(plane, wb, L.DIAG_EX2 | L.DIAG_EY2 | L.DIAG_EZ2 | L.DIAG_ENERGY)
     s.step(w.steps)
@@ -146,7 +146,7 @@ def test_plane_diagnostics_and_energy():
 
 
 def test_fused_equals_split():
-    w = W.parity_small()
+    w = W.parity_mid()
     a = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
     b = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=8, zchunk=0)
     a.step(w.steps)
@@ -173,7 +173,7 @@ def test_state_roundtrip_and_reset():
 
 
 def test_autotune_leaves_state_alone():
-    w = W.parity_small()
+    w = W.parity_mid()
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
     s.step(20)
     rows, zc = s.autotune(2)
