@@ -20,7 +20,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 BYTES_PER_CELL = 48            # read + write six FP32 field components
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "yee_tile_c2_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_interior_768x768x255_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc", "kernels_fused.hip")
 
 
@@ -128,7 +128,7 @@ def main():
     log(f"[bench] {args.steps} steps in {total_ms:.1f} ms -> {value:.1f} Gcell/s; "
         f"kernels: {prof}")
 
-    kin = prof.get("yee_tile")
+    kin = prof.get("fused_interior")
     roof = None
     if kin:
         avg_ms = kin[1] / kin[0]
@@ -137,7 +137,7 @@ def main():
         traffic = measured_traffic(info.interior_cells)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "yee_tile",
+                "traffic": traffic, "kernel": "fused_interior",
                 "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": info.interior_cells,
                 "bytes_per_launch": bytes_launch}
     step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9

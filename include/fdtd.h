@@ -126,8 +126,8 @@ typedef struct fdtd_info {
     int32_t n_source[6];         /* antenna points per component per plane   */
     int32_t n_slots;             /* antenna columns                          */
     int32_t kernel;              /* kernel in use                            */
-    int32_t tile_rows;           /* fused kernel: y rows per workgroup        */
-    int32_t tile_zchunk;         /* fused kernel: planes per workgroup        */
+    int32_t tile_rows;           /* fused kernel: y rows per wavefront        */
+    int32_t tile_zchunk;         /* fused kernel: z planes per wavefront      */
     int64_t step;                /* completed steps                           */
     int64_t device_bytes;        /* device memory held by the context         */
     int64_t interior_cells;      /* cells per step updated by the fused kernel */
@@ -213,9 +213,10 @@ int fdtd_get_info(const fdtd_ctx *ctx, fdtd_info *out);
  * to host_out[ny*nx]. Requires an injector. */
 int fdtd_analytic_ey2(fdtd_ctx *ctx, float *host_out, int64_t n);
 
-/* Select the fused kernel's tile shape explicitly: y rows per workgroup (one
- * wavefront per row) in {8, 16}; z chunk in planes, 0 = whole z. Returns
- * FDTD_EINVAL otherwise. */
+/* Select the fused kernel's tile shape explicitly: y rows per wavefront in
+ * {4, 8} (a wavefront covers 64 x cells and marches along z); z chunk in
+ * planes per wavefront, 0 = the whole z extent. Returns FDTD_EINVAL
+ * otherwise. */
 int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
 
 /* Time candidate tile shapes on the live problem (the state is restored) and

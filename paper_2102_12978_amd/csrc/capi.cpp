@@ -211,7 +211,7 @@ void ensure_time_tables(fdtd_ctx* c, long long upto) {
 // around it (the whole grid when there is no interior or for the split
 // kernel choice).
 Frame interior_of(const fdtd_ctx* c) {
-    if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0, 0};
+    if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0};
     return fused_interior_rect(c->p, c->rows);
 }
 
@@ -323,7 +323,7 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
         p.nx = grid->nx;
         p.ny = grid->ny;
         p.nz = grid->nz;
-        p.pitch = (grid->nx + 15) / 16 * 16;
+        p.pitch = (grid->nx + 63) / 64 * 64;   // 256-byte rows
         p.npml = grid->bc_xy == FDTD_BC_CPML ? grid->cpml_cells : 0;
         p.periodic = grid->bc_xy == FDTD_BC_PERIODIC;
         p.plane = -1;

@@ -109,13 +109,10 @@ struct LaunchTimer {
     virtual ~LaunchTimer() {}
 };
 
-// Rectangle of cells [x0, x1) × [y0, y1). For the split kernels with stride 0
-// it is excluded (all zero: the split kernels cover the whole grid); with a
-// stride > 0 the split H kernel runs on the last column of each stride-wide
-// segment of the rectangle.
+// Rectangle of cells [x0, x1) × [y0, y1) that the split kernels leave out
+// (all zero: the split kernels cover the whole grid).
 struct Frame {
     int x0, x1, y0, y1;
-    int stride;
 };
 
 // Fused interior kernel (kernels_fused.hip); rows per wavefront: 4 or 8.
@@ -124,7 +121,7 @@ int fused_interior_tiles(const Problem& p, int rows, int zchunk);
 hipError_t launch_fused_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
                                  double* epart, hipStream_t s, LaunchTimer* timer);
 
-// Split kernels over a frame or segment columns (kernels_split.hip)
+// Split kernels over the frame around a rectangle (kernels_split.hip)
 long long frame_columns(const Problem& p, const Frame& fr);
 int split_partial_count(const Problem& p, const Frame& fr);
 hipError_t launch_split_frame(const Problem& p, long long n, int parity, const Frame& fr,

@@ -5,15 +5,17 @@
 // CPML slab and no periodic wrap in x/y; the frame around it runs through
 // the split kernels (kernels_split.hip), which carry every boundary case.
 //
-// Work decomposition (CDNA4, wave64). Every wavefront is independent (no LDS,
-// no barriers): it owns a block of 64 x cells (one 256-byte aligned row
-// segment, so every load and store is two whole 128-byte lines) × TY y rows
-// and marches along z over a chunk of planes, keeping two planes of each
-// field in registers.
+// Work decomposition (CDNA4, wave64). A wavefront owns a block of 64 x cells
+// (a 256-byte row segment starting on a 128-byte line, so every load and
+// store covers whole lines) × TY y rows and marches along z over a chunk of
+// planes, keeping two planes of each field in registers.
 //   * x: lane l holds x = x0 + l; x neighbours move between lanes with
-//     cross-lane shuffles. Lane 0 fetches H at x0-1 with single-lane loads;
-//     lane 63 forms E_new(E_y, E_z) at x0+64 from single-lane loads, the
-//     value its H update needs.
+//     cross-lane shuffles. A workgroup holds four x-adjacent wavefronts; the
+//     values their edge lanes need from the neighbouring wavefront (H at
+//     x0-1 for lane 0, E_new at x0+64 for lane 63) pass through a small
+//     double-buffered LDS exchange, one barrier per plane. The outermost
+//     wavefronts of the group load H at x0-1 with single-lane loads and form
+//     E_new at x0+64 from single-lane loads.
 //   * y: each lane holds rows j0-1 .. j0+TY of H and j0 .. j0+TY of E in
 //     registers; E_new of row j0+TY is recomputed for the H update of the
 //     last owned row.
@@ -31,8 +33,8 @@ namespace bfdtd {
 
 namespace {
 
-constexpr int WAVES_PER_BLOCK = 4;
-constexpr int SEG = 64;   // x cells per wavefront
+constexpr int WAVES = 4;   // x-adjacent wavefronts per workgroup
+constexpr int SEG = 64;    // x cells per wavefront
 
 __device__ __forceinline__ float ldo(const float* base, unsigned boff) {
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
@@ -41,6 +43,12 @@ __device__ __forceinline__ float ldo(const float* base, unsigned boff) {
 __device__ __forceinline__ void sto(float* base, unsigned boff, float v) {
     *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
 }
+
+// Interior geometry: segment s covers x in [x_org + 64 s, x_org + 64 s + 64),
+// row group g covers y in [y_org + TY g, y_org + TY g + TY).
+struct Interior {
+    int x_org, y_org, nseg, nrow, ncz, cz;
+};
 
 template <int TY>
 struct Tile {
@@ -51,9 +59,9 @@ struct Tile {
     const float* fo[6];    // component bases, old parity
     float* fw[6];          // component bases, new parity
 
-    __device__ Tile(const Problem& pp, int par, int seg, int jj0) : p(pp), j0(jj0) {
+    __device__ Tile(const Problem& pp, int par, int x0, int jj0) : p(pp), j0(jj0) {
         lane = threadIdx.x & 63;
-        x = SEG * seg + lane;
+        x = x0 + lane;
 #pragma unroll
         for (int r = -1; r <= TY; ++r) ro[r + 1] = 4u * (unsigned)((j0 + r) * p.pitch + x);
         pstride = 4u * (unsigned)(p.ny * p.pitch);
@@ -78,14 +86,24 @@ struct Tile {
     }
 };
 
-// E_new on plane kk, rows 0..TY (ex/ey/ez hold E_old on entry); hx/hy/hz are
-// H_old(kk) (rows -1..TY, 0..TY, -1..TY), hxm/hym H_old(kk-1). Lane 0 takes
-// H at x0-1 from the column loads.
+// LDS exchange between x-adjacent wavefronts, double-buffered by iteration.
 template <int TY>
-__device__ __forceinline__ void e_plane(const Problem& p, const Tile<TY>& T, long long n, int kk,
+struct Exchange {
+    float hy[2][WAVES][TY + 1];   // H_y at x0+63 of wave w (rows 0..TY)
+    float hz[2][WAVES][TY];       // H_z at x0+63 of wave w (rows 0..TY-1)
+    float ey[2][WAVES][TY];       // E_new_y at x0 of wave w (rows 0..TY-1)
+    float ez[2][WAVES][TY];       // E_new_z at x0 of wave w
+};
+
+// E_new on plane kk, rows 0..TY (ex/ey/ez hold E_old on entry); hx/hy/hz are
+// H_old(kk) (rows -1..TY, 0..TY, -1..TY), hxm/hym H_old(kk-1); hyl/hzl: H at
+// x0-1 for lane 0.
+template <int TY>
+__device__ __forceinline__ void e_plane(const Problem& p, int lane, long long n, int kk,
                                         const int (&slot)[TY + 1], const float (&hx)[TY + 2],
                                         const float (&hy)[TY + 1], const float (&hz)[TY + 2],
                                         const float (&hxm)[TY], const float (&hym)[TY + 1],
+                                        const float (&hyl)[TY + 1], const float (&hzl)[TY],
                                         float (&ex)[TY + 1], float (&ey)[TY], float (&ez)[TY + 1]) {
     float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
     if (p.colmap) {
@@ -93,19 +111,11 @@ __device__ __forceinline__ void e_plane(const Problem& p, const Tile<TY>& T, lon
         pt0 = cmul(p.zph[2 * kk], t);
         pt1 = cmul(p.zph[2 * kk + 1], t);
     }
-    float hzl[TY], hyl[TY + 1];
-    if (T.lane == 0) {
-#pragma unroll
-        for (int r = 0; r <= TY; ++r) {
-            hyl[r] = T.ld_left(HY, kk, r);
-            if (r < TY) hzl[r] = T.ld_left(HZ, kk, r);
-        }
-    }
 #pragma unroll
     for (int r = 0; r <= TY; ++r) {
         float hz_im = __shfl_up(hz[r + 1], 1, 64);
         float hy_im = __shfl_up(hy[r], 1, 64);
-        if (T.lane == 0) {
+        if (lane == 0) {
             hy_im = hyl[r];
             if (r < TY) hz_im = hzl[r];
         }
@@ -162,56 +172,82 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, const Tile<TY>& T
 }
 
 template <int TY>
-__device__ __forceinline__ void tile_step(const Problem& p, long long n, int par, int seg, int j0,
-                                          int kb, int ke, double* epart_slot) {
-    const Tile<TY> T(p, par, seg, j0);
+__global__ void __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 1)))
+fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_padded,
+                      double* epart) {
+    __shared__ Exchange<TY> X;
+    // ---- which tile: hardware block b runs on XCD b % 8 ----------------
+    const int ngrp = (I.nseg + WAVES - 1) / WAVES;
+    const int lb = (blockIdx.x % 8) * (nblocks_padded / 8) + blockIdx.x / 8;
+    if (lb >= ngrp * I.nrow * I.ncz) return;                   // whole workgroup
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = lb % ngrp;
+    const int sy = (lb / ngrp) % I.nrow;
+    const int kb = (lb / (ngrp * I.nrow)) * I.cz;
+    const int ke = min(kb + I.cz, p.nz);
+    const int seg = grp * WAVES + w;
+    const bool active = seg < I.nseg;                          // uniform per wave
+    const int seg_last = min(grp * WAVES + WAVES, I.nseg) - 1;
+    const bool left_global = w == 0;                           // H at x0-1 from memory
+    const bool right_global = seg == seg_last;                 // E at x0+64 formed here
+    const int j0 = I.y_org + sy * TY;
+    const Tile<TY> T(p, par, I.x_org + SEG * (active ? seg : 0), j0);
+    const int lane = T.lane;
     const int nz = p.nz, nx = p.nx, ny = p.ny;
-    const bool right = T.lane == 63;
+    const bool right = lane == 63;
+    double* epart_slot = epart ? epart + ((size_t)lb * WAVES + w) : nullptr;
 
     int slot[TY + 1], slot_h[TY];
 #pragma unroll
     for (int r = 0; r <= TY; ++r)
-        slot[r] = p.colmap ? p.colmap[(size_t)(j0 + r) * nx + T.x] : -1;
+        slot[r] = (p.colmap && active) ? p.colmap[(size_t)(j0 + r) * nx + T.x] : -1;
 #pragma unroll
     for (int r = 0; r < TY; ++r)
-        slot_h[r] = (p.colmap && right) ? p.colmap[(size_t)(j0 + r) * nx + T.x + 1] : -1;
-    float hxh[TY], eyh[TY], ezh[TY];   // lane 63: H_x(k), E_new(k) at x0+64
+        slot_h[r] = (p.colmap && active && right && right_global)
+                        ? p.colmap[(size_t)(j0 + r) * nx + T.x + 1] : -1;
 
-    // ---- prologue: E_new(kb) ------------------------------------------
     float hcx[TY], hcy[TY + 1], hcz[TY];      // H_old(k), kept for the H update
     float ecx[TY + 1], ecy[TY], ecz[TY + 1];  // E_new(k)
-    {
-        const int km = kb == 0 ? nz - 1 : kb - 1;
-        float hx[TY + 2], hy[TY + 1], hz[TY + 2], hxm[TY], hym[TY + 1];
-#pragma unroll
-        for (int r = -1; r <= TY; ++r) {
-            hx[r + 1] = T.ld(HX, kb, r);
-            hz[r + 1] = T.ld(HZ, kb, r);
-            if (r >= 0) {
-                hy[r] = T.ld(HY, kb, r);
-                hym[r] = T.ld(HY, km, r);
-                ecx[r] = T.ld(EX, kb, r);
-                ecz[r] = T.ld(EZ, kb, r);
-            }
-            if (r >= 0 && r < TY) {
-                hxm[r] = T.ld(HX, km, r);
-                ecy[r] = T.ld(EY, kb, r);
-            }
-        }
-        e_plane<TY>(p, T, n, kb, slot, hx, hy, hz, hxm, hym, ecx, ecy, ecz);
+    float hxh[TY], eyh[TY], ezh[TY];          // lane 63: H_x(k), E_new(k) at x0+64
+    float hyl[TY + 1], hzl[TY];               // lane 0: H at x0-1
+
+    // H of the own lane 63 to the exchange (for the right neighbour's lane 0)
+    auto put_h = [&](int buf, const float (&hy)[TY + 1], const float (&hz)[TY + 2]) {
         if (right) {
 #pragma unroll
-            for (int r = 0; r < TY; ++r) hxh[r] = T.ld_right(HX, km, r);
-            e_halo_right<TY>(p, T, n, kb, slot_h, hy, hz, hxh, eyh, ezh);
-        }
+            for (int r = 0; r <= TY; ++r) X.hy[buf][w][r] = hy[r];
 #pragma unroll
-        for (int r = 0; r < TY; ++r) {
-            hcx[r] = hx[r + 1];
-            hcy[r] = hy[r];
-            hcz[r] = hz[r + 1];
+            for (int r = 0; r < TY; ++r) X.hz[buf][w][r] = hz[r + 1];
         }
-        hcy[TY] = hy[TY];
-    }
+    };
+    // H at x0-1 for lane 0: memory for the first wave, exchange otherwise
+    auto get_left = [&](int buf, int kk) {
+        if (lane == 0) {
+            if (left_global) {
+#pragma unroll
+                for (int r = 0; r <= TY; ++r) {
+                    hyl[r] = T.ld_left(HY, kk, r);
+                    if (r < TY) hzl[r] = T.ld_left(HZ, kk, r);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r <= TY; ++r) {
+                    hyl[r] = X.hy[buf][w - 1][r];
+                    if (r < TY) hzl[r] = X.hz[buf][w - 1][r];
+                }
+            }
+        }
+    };
+    auto put_e = [&](int buf, const float (&ey)[TY], const float (&ez)[TY + 1]) {
+        if (lane == 0) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                X.ey[buf][w][r] = ey[r];
+                X.ez[buf][w][r] = ez[r];
+            }
+        }
+    };
 
     double en = 0.0;
     auto store_e = [&](int kk, const float (&ex)[TY + 1], const float (&ey)[TY],
@@ -231,30 +267,81 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
             }
         }
     };
-    store_e(kb, ecx, ecy, ecz);
+
+    // ---- prologue: E_new(kb) ------------------------------------------
+    {
+        const int km = kb == 0 ? nz - 1 : kb - 1;
+        float hx[TY + 2], hy[TY + 1], hz[TY + 2], hxm[TY], hym[TY + 1];
+        if (active) {
+#pragma unroll
+            for (int r = -1; r <= TY; ++r) {
+                hx[r + 1] = T.ld(HX, kb, r);
+                hz[r + 1] = T.ld(HZ, kb, r);
+                if (r >= 0) {
+                    hy[r] = T.ld(HY, kb, r);
+                    hym[r] = T.ld(HY, km, r);
+                    ecx[r] = T.ld(EX, kb, r);
+                    ecz[r] = T.ld(EZ, kb, r);
+                }
+                if (r >= 0 && r < TY) {
+                    hxm[r] = T.ld(HX, km, r);
+                    ecy[r] = T.ld(EY, kb, r);
+                }
+            }
+            put_h(0, hy, hz);
+        }
+        __syncthreads();
+        if (active) {
+            get_left(0, kb);
+            e_plane<TY>(p, lane, n, kb, slot, hx, hy, hz, hxm, hym, hyl, hzl, ecx, ecy, ecz);
+            put_e(0, ecy, ecz);
+            if (right && right_global) {
+#pragma unroll
+                for (int r = 0; r < TY; ++r) hxh[r] = T.ld_right(HX, km, r);
+                e_halo_right<TY>(p, T, n, kb, slot_h, hy, hz, hxh, eyh, ezh);
+            }
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                hcx[r] = hx[r + 1];
+                hcy[r] = hy[r];
+                hcz[r] = hz[r + 1];
+            }
+            hcy[TY] = hy[TY];
+            store_e(kb, ecx, ecy, ecz);
+        }
+    }
     const float2 th = p.colmap ? p.tH[n] : make_float2(0.f, 0.f);
 
-    for (int k = kb; k < ke; ++k) {
+    int it = 0;
+    for (int k = kb; k < ke; ++k, ++it) {
         const int kn = k + 1 == nz ? 0 : k + 1;
-        // ---- load H_old(k+1), E_old(k+1); form E_new(k+1) -------------
+        const int bn = (it + 1) & 1, bk = it & 1;
         float hx[TY + 2], hy[TY + 1], hz[TY + 2];
         float enx[TY + 1], eny[TY], enz[TY + 1];
+        if (active) {
 #pragma unroll
-        for (int r = -1; r <= TY; ++r) {
-            hx[r + 1] = T.ld(HX, kn, r);
-            hz[r + 1] = T.ld(HZ, kn, r);
-            if (r >= 0) {
-                hy[r] = T.ld(HY, kn, r);
-                enx[r] = T.ld(EX, kn, r);
-                enz[r] = T.ld(EZ, kn, r);
+            for (int r = -1; r <= TY; ++r) {
+                hx[r + 1] = T.ld(HX, kn, r);
+                hz[r + 1] = T.ld(HZ, kn, r);
+                if (r >= 0) {
+                    hy[r] = T.ld(HY, kn, r);
+                    enx[r] = T.ld(EX, kn, r);
+                    enz[r] = T.ld(EZ, kn, r);
+                }
+                if (r >= 0 && r < TY) eny[r] = T.ld(EY, kn, r);
             }
-            if (r >= 0 && r < TY) eny[r] = T.ld(EY, kn, r);
+            put_h(bn, hy, hz);
         }
-        e_plane<TY>(p, T, n, kn, slot, hx, hy, hz, hcx, hcy, enx, eny, enz);
+        __syncthreads();
+        if (!active) continue;
+        // ---- E_new(k+1) -------------------------------------------------
+        get_left(bn, kn);
+        e_plane<TY>(p, lane, n, kn, slot, hx, hy, hz, hcx, hcy, hyl, hzl, enx, eny, enz);
+        put_e(bn, eny, enz);
         float eyh_n[TY], ezh_n[TY];
-        if (right) e_halo_right<TY>(p, T, n, kn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
+        if (right && right_global) e_halo_right<TY>(p, T, n, kn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
 
-        // ---- H_new(k) ---------------------------------------------------
+        // ---- H_new(k): E_new(k) at x0+64 from the exchange or the halo --
         float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
         if (p.colmap) {
             qt0 = cmul(p.zph[2 * k], th);
@@ -265,8 +352,13 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
             float ey_ip = __shfl_down(ecy[r], 1, 64);
             float ez_ip = __shfl_down(ecz[r], 1, 64);
             if (right) {
-                ey_ip = eyh[r];
-                ez_ip = ezh[r];
+                if (right_global) {
+                    ey_ip = eyh[r];
+                    ez_ip = ezh[r];
+                } else {
+                    ey_ip = X.ey[bk][w + 1][r];
+                    ez_ip = X.ez[bk][w + 1][r];
+                }
             }
             // H_x -= S_y Δ_y E_z - S_z Δ_z E_y
             float vx = hcx[r] - (p.sy * (ecz[r + 1] - ecz[r]) - p.sz * (eny[r] - ecy[r]));
@@ -300,7 +392,7 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
             ecx[r] = enx[r];
             ecz[r] = enz[r];
         }
-        if (right) {
+        if (right && right_global) {
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
                 eyh[r] = eyh_n[r];
@@ -310,80 +402,55 @@ __device__ __forceinline__ void tile_step(const Problem& p, long long n, int par
     }
     if (epart_slot) {
         en = wave_sum(en);
-        if (T.lane == 0) *epart_slot = en;
+        if (lane == 0) *epart_slot = en;
     }
 }
 
-// Interior tiles: seg in [sx0, sx0 + nsx), sy in [sy0, sy0 + nsy), ncz z chunks.
-template <int TY>
-__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK)
-__attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 1))) fused_interior_kernel(
-    Problem p, long long n, int par, int sx0, int sy0, int nsx, int nsy,
-                      int ncz, int cz, int nblocks_padded, double* epart) {
-    // hardware block b runs on XCD b % 8; give each XCD a contiguous run
-    const int b = blockIdx.x;
-    const int lb = (b % 8) * (nblocks_padded / 8) + b / 8;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = lb * WAVES_PER_BLOCK + wave;
-    if (t >= nsx * nsy * ncz) return;
-    const int seg = sx0 + t % nsx;
-    const int sy = sy0 + (t / nsx) % nsy;
-    const int kb = (t / (nsx * nsy)) * cz;
-    const int ke = min(kb + cz, p.nz);
-    tile_step<TY>(p, n, par, seg, sy * TY, kb, ke, epart ? epart + t : nullptr);
-}
-
-// Interior tile rectangle [sx0, sx1) × [sy0, sy1) in tile units (may be empty):
-// every lane x = 64 seg .. 64 seg + 63, the columns x0 - 1 and x0 + 64 and
-// every row j0 - 1 .. j0 + TY lie in [max(npml, 1), n - npml - 1].
-void interior_tiles(const Problem& p, int rows, int* sx0, int* sx1, int* sy0, int* sy1) {
-    *sx0 = *sx1 = *sy0 = *sy1 = 0;
-    if (p.periodic) return;
+// Interior: x0 - 1 >= m and every x0 on a 128-byte line; the last segment
+// keeps its column x0 + 64 inside too; rows j0 - 1 .. j0 + TY likewise,
+// m = max(npml, 1), upper bound n - npml - 1.
+Interior interior(const Problem& p, int rows, int zchunk) {
+    Interior I{0, 0, 0, 0, 0, 0};
+    if (p.periodic) return I;
     const int m = p.npml > 0 ? p.npml : 1;
-    const int a = (m + 1 + SEG - 1) / SEG;
-    const int b = (p.nx - p.npml - SEG - 1) >= 0 ? (p.nx - p.npml - SEG - 1) / SEG + 1 : 0;
-    const int c = (m + 1 + rows - 1) / rows;
-    const int d = (p.ny - p.npml - 1 - rows) >= 0 ? (p.ny - p.npml - 1 - rows) / rows + 1 : 0;
-    if (a < b && c < d) {
-        *sx0 = a; *sx1 = b; *sy0 = c; *sy1 = d;
-    }
+    const int hi_x = p.nx - p.npml - 1, hi_y = p.ny - p.npml - 1;
+    I.x_org = (m + 1 + 31) / 32 * 32;
+    I.y_org = m + 1;
+    I.nseg = hi_x - I.x_org - SEG + 1 >= 0 ? (hi_x - I.x_org - SEG) / SEG + 1 : 0;
+    I.nrow = hi_y - I.y_org - rows + 1 >= 0 ? (hi_y - I.y_org - rows) / rows + 1 : 0;
+    I.cz = zchunk > 0 ? min(zchunk, p.nz) : p.nz;
+    I.ncz = (p.nz + I.cz - 1) / I.cz;
+    if (I.nseg <= 0 || I.nrow <= 0) I.nseg = I.nrow = 0;
+    return I;
 }
 
-int zchunks(const Problem& p, int zchunk, int* cz) {
-    *cz = zchunk > 0 ? min(zchunk, p.nz) : p.nz;
-    return (p.nz + *cz - 1) / *cz;
+int group_count(const Interior& I) {
+    return ((I.nseg + WAVES - 1) / WAVES) * I.nrow * I.ncz;
 }
 
 template <int TY>
 hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, double* epart,
                        hipStream_t s, LaunchTimer* timer) {
-    int sx0, sx1, sy0, sy1, cz;
-    interior_tiles(p, TY, &sx0, &sx1, &sy0, &sy1);
-    const int ncz = zchunks(p, zchunk, &cz);
-    const int ni = (sx1 - sx0) * (sy1 - sy0) * ncz;
-    if (ni <= 0) return hipSuccess;
-    const int nb = (ni + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    const Interior I = interior(p, TY, zchunk);
+    const int nb = group_count(I);
+    if (nb <= 0) return hipSuccess;
     const int nbp = (nb + 7) / 8 * 8;
     if (timer) timer->mark("fused_interior");
-    hipLaunchKernelGGL(fused_interior_kernel<TY>, dim3(nbp), dim3(64 * WAVES_PER_BLOCK), 0, s, p,
-                       n, parity, sx0, sy0, sx1 - sx0, sy1 - sy0, ncz, cz, nbp, epart);
+    hipLaunchKernelGGL(fused_interior_kernel<TY>, dim3(nbp), dim3(64 * WAVES), 0, s, p, n,
+                       parity, I, nbp, epart);
     return hipGetLastError();
 }
 
 }  // namespace
 
 Frame fused_interior_rect(const Problem& p, int rows) {
-    int sx0, sx1, sy0, sy1;
-    interior_tiles(p, rows, &sx0, &sx1, &sy0, &sy1);
-    if (sx0 >= sx1) return Frame{0, 0, 0, 0, 0};
-    // stride is 0: the rectangle is the region the split frame pass excludes
-    return Frame{SEG * sx0, SEG * sx1, rows * sy0, rows * sy1, 0};
+    const Interior I = interior(p, rows, 0);
+    if (I.nseg <= 0) return Frame{0, 0, 0, 0};
+    return Frame{I.x_org, I.x_org + SEG * I.nseg, I.y_org, I.y_org + rows * I.nrow};
 }
 
 int fused_interior_tiles(const Problem& p, int rows, int zchunk) {
-    int sx0, sx1, sy0, sy1, cz;
-    interior_tiles(p, rows, &sx0, &sx1, &sy0, &sy1);
-    return (sx1 - sx0) * (sy1 - sy0) * zchunks(p, zchunk, &cz);
+    return group_count(interior(p, rows, zchunk)) * WAVES;
 }
 
 hipError_t launch_fused_interior(const Problem& p, long long n, int parity, int rows, int zchunk,

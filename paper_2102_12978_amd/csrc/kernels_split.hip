@@ -6,9 +6,7 @@
 // The cells are enumerated as a flat list of (x, y) columns of a frame
 // around an excluded rectangle (bottom rows y < y0, top rows y >= y1, then
 // the left x < x0 and right x >= x1 strips of the rows in between); an empty
-// rectangle makes the frame the whole grid. With a stride, the list is
-// instead the last column of every stride-wide segment of the rectangle
-// (H update only).
+// rectangle makes the frame the whole grid.
 #include <hip/hip_runtime.h>
 
 #include "yee_cell.hpp"
@@ -30,13 +28,6 @@ __device__ __forceinline__ void block_energy(double v, double* out) {
 
 __device__ __forceinline__ bool frame_column(const Frame& fr, int nx, int ny, long long c, int* x,
                                              int* y) {
-    if (fr.stride > 0) {   // the last column of every segment of the rectangle
-        const int nseg = (fr.x1 - fr.x0) / fr.stride;
-        if (c >= (long long)nseg * (fr.y1 - fr.y0)) return false;
-        *y = fr.y0 + (int)(c / nseg);
-        *x = fr.x0 + fr.stride * (int)(c % nseg) + fr.stride - 1;
-        return true;
-    }
     const long long nb = (long long)fr.y0 * nx;
     const long long nt = (long long)(ny - fr.y1) * nx;
     const long long nl = (long long)(fr.y1 - fr.y0) * fr.x0;
@@ -165,14 +156,13 @@ split_h_kernel(Problem p, long long n, int par, Frame fr, long long ncols, doubl
 }  // namespace
 
 long long frame_columns(const Problem& p, const Frame& fr) {
-    if (fr.stride > 0) return (long long)((fr.x1 - fr.x0) / fr.stride) * (fr.y1 - fr.y0);
     return (long long)fr.y0 * p.nx + (long long)(p.ny - fr.y1) * p.nx +
            (long long)(fr.y1 - fr.y0) * (fr.x0 + p.nx - fr.x1);
 }
 
 int split_partial_count(const Problem& p, const Frame& fr) {
     const long long nc = frame_columns(p, fr);
-    return nc == 0 ? 0 : (fr.stride > 0 ? 1 : 2) * (int)((nc + BT - 1) / BT) * p.nz;
+    return nc == 0 ? 0 : 2 * (int)((nc + BT - 1) / BT) * p.nz;
 }
 
 hipError_t launch_split_frame(const Problem& p, long long n, int parity, const Frame& fr,
@@ -181,12 +171,6 @@ hipError_t launch_split_frame(const Problem& p, long long n, int parity, const F
     if (nc == 0) return hipSuccess;
     dim3 grid((unsigned)((nc + BT - 1) / BT), p.nz, 1);
     const size_t nb = (size_t)grid.x * grid.y;
-    if (fr.stride > 0) {   // H only: the segment columns left provisional by the fused kernel
-        if (timer) timer->mark("fixup_h");
-        hipLaunchKernelGGL(split_h_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, epart);
-        if (timer) timer->mark(nullptr);
-        return hipGetLastError();
-    }
     if (timer) timer->mark(fr.x1 > 0 ? "frame_e" : "split_e");
     hipLaunchKernelGGL(split_e_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, epart);
     hipError_t e = hipGetLastError();

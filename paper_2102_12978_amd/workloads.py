@@ -169,6 +169,14 @@ def parity_mid():
                     ramp_periods=2.0)
 
 
+def parity_wide():
+    """Seven fused segments (two workgroups of four x-adjacent wavefronts, the
+    second one short): 540×80×(16 hint), 10-cell CPML, θ = 22°, m = 1,
+    antenna of radius 30Δx across the workgroup boundary at x = 288, 40 steps."""
+    return Workload("p_540x80x16_theta22_m1", 540, 80, 16, 14.0, 22.0, 1, 30.0, 3.0, 10, 40,
+                    ramp_periods=2.0)
+
+
 def parity_small():
     """Several-tile case with ragged edges: 100×72×(40 hint), source in the
     interior, 16-cell CPML, θ = 18°, m = 1, 60 steps."""

@@ -62,6 +62,34 @@ def test_fused_interior_frame_and_fixup(rows, zchunk):
     s.close()
 
 
+@pytest.mark.parametrize("rows,zchunk", [(4, 0), (8, 5)])
+def test_fused_partial_workgroup(rows, zchunk):
+    """540×80: a full and a short group of x-adjacent wavefronts; halo values
+    cross wavefronts through LDS inside a group and through memory between
+    groups, with antenna points on both sides of the group boundary."""
+    w = W.parity_wide()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=rows, zchunk=zchunk)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
+def test_fused_partial_workgroup_random_start():
+    """Random fields everywhere (walls zeroed) on the 540×80 grid, so every
+    lane-0 / lane-63 halo value is nonzero from the first step."""
+    w = W.parity_wide()
+    w.steps = 12
+    g, st0 = GC.random_start(w, P.BC_CPML, seed=6)
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0)
+    for i, c in enumerate(GC.COMPS):
+        s.set_state(i, st0.f[c])
+    s.step(w.steps)
+    _, st = GC.oracle_run(w, w.steps, state=st0)
+    _compare(s, st, g)
+    s.close()
+
+
 def test_ragged_small_grid():
     """100×72: too small for an interior, all cells go through the frame."""
     w = W.parity_small()
