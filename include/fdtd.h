@@ -240,6 +240,75 @@ int fdtd_profile_enable(fdtd_ctx *ctx, int32_t on);
 /* Copy up to max entries; *count receives the number of kernel names. */
 int fdtd_profile_read(fdtd_ctx *ctx, fdtd_kernel_profile *out, int32_t max, int32_t *count);
 
+/* ---- batch: many independent instances advanced together -----------------
+ * A batch owns `count` solver contexts of uneven grid size, cone angle and
+ * order (each made as by fdtd_create with FDTD_KERNEL_SPLIT on the batch's
+ * stream, then fdtd_set_injector) and advances them in lockstep. Every step
+ * is one E launch and one H launch that walk a single flattened list of work
+ * items (instance, block of `cols` flattened (x, y) columns, z range of
+ * `zchunk` planes) with a persistent grid; the per-cell arithmetic is that
+ * of the split kernels, so every instance evolves bit-identically to a
+ * single-domain FDTD_KERNEL_SPLIT run of the same problem. Runs of
+ * graph_steps steps are recorded once into a HIP graph and replayed; the
+ * step index lives in a device counter so a replay stays valid. */
+typedef struct fdtd_batch fdtd_batch;
+
+typedef struct fdtd_batch_info {
+    int32_t count;               /* instances                                  */
+    int32_t tile_cols;           /* columns per work item (= workgroup size)  */
+    int32_t tile_zchunk;         /* z planes per work item, 0 = whole z        */
+    int32_t work_items;          /* flattened work list length                 */
+    int32_t blocks;              /* persistent grid (workgroups per launch)    */
+    int32_t graph_steps;         /* steps per graph replay, 0 = no graphs      */
+    int64_t cells;               /* sum of nx*ny*nz over the instances         */
+    int64_t step;                /* completed steps                            */
+    int64_t device_bytes;        /* device memory held by batch and instances  */
+} fdtd_batch_info;
+
+/* Create a batch. grids[count] (their stream and kernel fields are ignored:
+ * the batch's stream and the split kernel choice are used); injectors is
+ * NULL (no antennas) or holds count entries. Every instance is validated as
+ * by fdtd_create / fdtd_set_injector; the first failure is returned with
+ * the instance index in fdtd_batch_last_error(NULL). On failure *out is
+ * NULL and nothing is kept. */
+int fdtd_batch_create(int32_t count, const fdtd_grid *grids, const fdtd_injector *injectors,
+                      void *stream, fdtd_batch **out);
+
+/* Free the batch and its instances. NULL-safe. */
+int fdtd_batch_destroy(fdtd_batch *b);
+
+/* Message of the last failure on b (or of the last failed create when b is
+ * NULL). */
+const char *fdtd_batch_last_error(const fdtd_batch *b);
+
+/* Borrowed handle of instance q (NULL when out of range), valid until the
+ * batch is destroyed. Read-backs (fdtd_get_state, fdtd_fluence, _count,
+ * fdtd_get_info, fdtd_analytic_ey2), fdtd_set_state, fdtd_set_diagnostics
+ * (window steps count from the batch's step 0), fdtd_set_injector and
+ * fdtd_set_sector_weights work on it as on any context; fdtd_step,
+ * fdtd_reset, fdtd_set_tile, fdtd_autotune and fdtd_destroy return
+ * FDTD_ESTATE. The energy diagnostic is not computed for batch instances. */
+fdtd_ctx *fdtd_batch_instance(fdtd_batch *b, int32_t q);
+
+/* Advance every instance nsteps steps (asynchronous on the batch's stream). */
+int fdtd_batch_step(fdtd_batch *b, int64_t nsteps);
+
+/* Work-item shape: cols in {64, 128, 256}, zchunk >= 0 (0 = whole z). */
+int fdtd_batch_set_tile(fdtd_batch *b, int32_t cols, int32_t zchunk);
+
+/* Steps recorded per graph: an even number in [2, 1000], or 0 to launch
+ * every step directly. */
+int fdtd_batch_set_graph_steps(fdtd_batch *b, int32_t steps);
+
+/* Time every work-item shape (cols x zchunk in {64, 128, 256} x
+ * {0, 16, 8, 4, 1})
+ * for steps_per_trial steps on the live state, keep the fastest. Trials
+ * write only the buffers of the next parity, so the state is unchanged. */
+int fdtd_batch_autotune(fdtd_batch *b, int32_t steps_per_trial, int32_t *best_cols,
+                        int32_t *best_zchunk);
+
+int fdtd_batch_get_info(const fdtd_batch *b, fdtd_batch_info *out);
+
 #ifdef __cplusplus
 }
 #endif

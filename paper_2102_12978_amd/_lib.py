@@ -55,7 +55,17 @@ class KernelProfile(ctypes.Structure):
                 ("total_ms", ctypes.c_double)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+                ("tile_zchunk", ctypes.c_int32), ("work_items", ctypes.c_int32),
+                ("blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("cells", ctypes.c_int64), ("step", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
 _CTX = ctypes.c_void_p
+_BATCH = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
 _SIGS = {
     "fdtd_version": (ctypes.c_char_p, []),
     "fdtd_fit_periodic_z": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -83,6 +93,17 @@ _SIGS = {
     "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
+    "fdtd_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Grid),
+                                         ctypes.POINTER(Injector), ctypes.c_void_p,
+                                         ctypes.POINTER(_BATCH)]),
+    "fdtd_batch_destroy": (ctypes.c_int, [_BATCH]),
+    "fdtd_batch_last_error": (ctypes.c_char_p, [_BATCH]),
+    "fdtd_batch_instance": (_CTX, [_BATCH, ctypes.c_int32]),
+    "fdtd_batch_step": (ctypes.c_int, [_BATCH, ctypes.c_int64]),
+    "fdtd_batch_set_tile": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32]),
+    "fdtd_batch_set_graph_steps": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
+    "fdtd_batch_autotune": (ctypes.c_int, [_BATCH, ctypes.c_int32, _I32P, _I32P]),
+    "fdtd_batch_get_info": (ctypes.c_int, [_BATCH, ctypes.POINTER(BatchInfo)]),
 }
 
 _lib = None

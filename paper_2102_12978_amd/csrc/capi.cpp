@@ -10,158 +10,15 @@
 #include <string>
 #include <vector>
 
-#include "fdtd_internal.hpp"
+#include "context.hpp"
 
 using namespace bfdtd;
 
-
-// Event-pair timer for fdtd_profile_*: one event before each launch, the
-// next mark closes it.
-struct EventTimer : LaunchTimer {
-    hipStream_t stream = nullptr;
-    struct Rec {
-        std::string name;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> open_;
-    std::vector<std::pair<std::string, std::pair<long long, double>>> totals;
-    int pending = -1;
-    void mark(const char* name) override {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        (void)hipEventRecord(e, stream);
-        if (pending >= 0) open_[pending].b = e;
-        pending = -1;
-        if (name) {
-            open_.push_back(Rec{name, e, nullptr});
-            pending = (int)open_.size() - 1;
-        } else if (open_.empty() || open_.back().b != e) {
-            (void)hipEventDestroy(e);
-        }
-    }
-    void collect() {
-        std::vector<hipEvent_t> seen;
-        for (auto& r : open_) {
-            if (!r.b) continue;
-            (void)hipEventSynchronize(r.b);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, r.a, r.b);
-            bool found = false;
-            for (auto& t : totals)
-                if (t.first == r.name) {
-                    t.second.first += 1;
-                    t.second.second += ms;
-                    found = true;
-                }
-            if (!found) totals.push_back({r.name, {1, (double)ms}});
-        }
-        for (auto& r : open_) {
-            for (hipEvent_t e : {r.a, r.b}) {
-                if (!e) continue;
-                if (std::find(seen.begin(), seen.end(), e) == seen.end()) {
-                    seen.push_back(e);
-                    (void)hipEventDestroy(e);
-                }
-            }
-        }
-        open_.clear();
-        pending = -1;
-    }
-    ~EventTimer() override { collect(); }
-};
-
-struct fdtd_ctx {
-    fdtd_grid g{};
-    hipStream_t stream = nullptr;
-    int device = 0;
-    double ry = 1, rz = 1;
-    Problem p{};
-    std::vector<void*> allocs;
-    long long device_bytes = 0;
-    // antenna
-    bool has_inj = false;
-    Antenna ant;
-    int* colmap = nullptr;
-    float2* amp = nullptr;
-    float2* zph = nullptr;
-    float2* tE = nullptr;
-    float2* tH = nullptr;
-    long long t_cap = 0;
-    // diagnostics
-    int plane = -1;
-    long long wbegin = 0;
-    unsigned mask = 0;
-    long long count = 0;
-    double* fl = nullptr;
-    double* epart = nullptr;
-    int epart_cap = 0;
-    double* energy_dev = nullptr;
-    bool energy_valid = false;
-    // stepping
-    long long step = 0;
-    int parity = 0;
-    int kernel = FDTD_KERNEL_FUSED;
-    int rows = 4, zchunk = 0;
-    EventTimer* timer = nullptr;
-    std::string err;
-};
 
 namespace {
 
 thread_local std::string g_create_error;
 const char* kVersion = "besselfdtd 0.1 (gfx950)";
-
-struct Fail {
-    int code;
-    std::string msg;
-};
-
-void check(hipError_t e, const char* what) {
-    if (e != hipSuccess) {
-        int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? FDTD_ENOMEM
-                                                                              : FDTD_EDEVICE;
-        throw Fail{code, std::string(what) + ": " + hipGetErrorString(e)};
-    }
-}
-
-template <typename T>
-T* dalloc(fdtd_ctx* c, size_t count) {
-    if (count == 0) return nullptr;
-    void* ptr = nullptr;
-    check(hipMalloc(&ptr, count * sizeof(T)), "hipMalloc");
-    c->allocs.push_back(ptr);
-    c->device_bytes += (long long)(count * sizeof(T));
-    check(hipMemsetAsync(ptr, 0, count * sizeof(T), c->stream), "hipMemsetAsync");
-    return static_cast<T*>(ptr);
-}
-
-void dfree(fdtd_ctx* c, void* ptr) {
-    if (!ptr) return;
-    auto it = std::find(c->allocs.begin(), c->allocs.end(), ptr);
-    if (it != c->allocs.end()) c->allocs.erase(it);
-    (void)hipFree(ptr);
-}
-
-template <typename F>
-int guarded(fdtd_ctx* c, F&& f) {
-    try {
-        f();
-        return FDTD_OK;
-    } catch (const Fail& e) {
-        if (c) c->err = e.msg;
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        if (c) c->err = "host allocation failed";
-        return FDTD_ENOMEM;
-    } catch (...) {
-        if (c) c->err = "unexpected exception";
-        return FDTD_EDEVICE;
-    }
-}
-
-void need(bool ok, const std::string& msg, int code = FDTD_EINVAL) {
-    if (!ok) throw Fail{code, msg};
-}
 
 size_t state_elems(const fdtd_ctx* c, int which) {
     const Problem& p = c->p;
@@ -178,33 +35,6 @@ size_t state_elems(const fdtd_ctx* c, int which) {
 bool psi_is_x(int which) {
     return which == FDTD_PSI_EYX || which == FDTD_PSI_EZX || which == FDTD_PSI_HYX ||
            which == FDTD_PSI_HZX;
-}
-
-void ensure_time_tables(fdtd_ctx* c, long long upto) {
-    if (!c->has_inj || upto <= c->t_cap) return;
-    check(hipStreamSynchronize(c->stream), "sync");   // old tables may be in use
-    long long cap = std::max(upto, std::max(2 * c->t_cap, 1024LL));
-    std::vector<float2> te(cap), th(cap);
-    const double dt = c->g.courant;
-    for (long long n = 0; n < cap; ++n) {
-        double re, im;
-        time_factor(c->ant, (n + 1.0) * dt, &re, &im);
-        te[n] = make_float2((float)re, (float)im);
-        time_factor(c->ant, (n + 1.5) * dt, &re, &im);
-        th[n] = make_float2((float)re, (float)im);
-    }
-    dfree(c, c->tE);
-    dfree(c, c->tH);
-    c->tE = dalloc<float2>(c, cap);
-    c->tH = dalloc<float2>(c, cap);
-    check(hipMemcpyAsync(c->tE, te.data(), cap * sizeof(float2), hipMemcpyHostToDevice, c->stream),
-          "copy time table");
-    check(hipMemcpyAsync(c->tH, th.data(), cap * sizeof(float2), hipMemcpyHostToDevice, c->stream),
-          "copy time table");
-    check(hipStreamSynchronize(c->stream), "sync");
-    c->t_cap = cap;
-    c->p.tE = c->tE;
-    c->p.tH = c->tH;
 }
 
 // A fused step: the interior kernel, then the split kernels on the frame
@@ -368,6 +198,10 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
 
 int fdtd_destroy(fdtd_ctx* ctx) {
     if (!ctx) return FDTD_OK;
+    if (ctx->batch_owned) {
+        ctx->err = "instance is owned by its batch";
+        return FDTD_ESTATE;
+    }
     if (!ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
     delete ctx->timer;
     for (void* ptr : ctx->allocs) (void)hipFree(ptr);
@@ -469,6 +303,10 @@ int fdtd_set_diagnostics(fdtd_ctx* c, int32_t k_plane, int64_t window_begin_step
 
 int fdtd_step(fdtd_ctx* c, int64_t nsteps) {
     if (!c) return FDTD_EINVAL;
+    if (c->batch_owned) {
+        c->err = "instance is stepped by its batch";
+        return FDTD_ESTATE;
+    }
     return guarded(c, [&] {
         need(nsteps >= 0, "nsteps must be >= 0");
         ensure_time_tables(c, c->step + nsteps);
@@ -573,6 +411,10 @@ int fdtd_set_state(fdtd_ctx* c, int32_t which, const float* host, int64_t n) {
 
 int fdtd_reset(fdtd_ctx* c) {
     if (!c) return FDTD_EINVAL;
+    if (c->batch_owned) {
+        c->err = "instance is stepped by its batch";
+        return FDTD_ESTATE;
+    }
     return guarded(c, [&] {
         const Problem& p = c->p;
         for (int par = 0; par < 2; ++par) {
@@ -640,6 +482,10 @@ int fdtd_analytic_ey2(fdtd_ctx* c, float* host_out, int64_t n) {
 
 int fdtd_set_tile(fdtd_ctx* c, int32_t rows, int32_t zchunk) {
     if (!c) return FDTD_EINVAL;
+    if (c->batch_owned) {
+        c->err = "instance is stepped by its batch";
+        return FDTD_ESTATE;
+    }
     return guarded(c, [&] {
         need(rows == 4 || rows == 8, "rows must be 4 or 8");
         need(zchunk >= 0 && zchunk <= c->p.nz, "zchunk out of range");
@@ -652,6 +498,10 @@ int fdtd_set_tile(fdtd_ctx* c, int32_t rows, int32_t zchunk) {
 int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                   int32_t* best_zchunk) {
     if (!c) return FDTD_EINVAL;
+    if (c->batch_owned) {
+        c->err = "instance is stepped by its batch";
+        return FDTD_ESTATE;
+    }
     return guarded(c, [&] {
         need(steps_per_trial >= 1 && steps_per_trial <= 1000, "steps_per_trial out of range");
         need(c->kernel == FDTD_KERNEL_FUSED, "autotune applies to the fused kernel");

@@ -45,6 +45,7 @@ struct Problem {
     double* fl;                     // [3][ny][nx] plane sums (E_x², E_y², E_z²)
     float* rec;                     // E_y plane record (adjoint), or null
     long long rec_begin;            // first recorded step
+    long long win_begin;            // batched kernels: first step whose plane is accumulated
 };
 
 // Position of CPML memory q (P_* order) inside one parity's allocation.
@@ -128,5 +129,17 @@ hipError_t launch_split_frame(const Problem& p, long long n, int parity, const F
                               double* epart, hipStream_t s, LaunchTimer* timer);
 
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
+
+// Batched kernels over many instances (kernels_batch.hip). A work item is
+// (instance, first flattened column, k begin, k end); the E and H kernels
+// loop over the items with a persistent grid of `blocks` workgroups of
+// `cols` threads. The step index is *nctr + off (a device counter so that a
+// captured graph can be replayed); par is the parity read.
+hipError_t launch_batch_e(const Problem* probs, const int4* work, int nwork, int cols, int blocks,
+                          const long long* nctr, int off, int par, int diag, hipStream_t s);
+hipError_t launch_batch_h(const Problem* probs, const int4* work, int nwork, int cols, int blocks,
+                          const long long* nctr, int off, int par, hipStream_t s);
+hipError_t launch_batch_advance(long long* nctr, int by, hipStream_t s);
+int batch_blocks_per_cu(int cols);   // resident workgroups per CU of both batch kernels
 
 }  // namespace bfdtd

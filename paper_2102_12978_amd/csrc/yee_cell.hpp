@@ -1,7 +1,7 @@
 // Per-cell Yee updates with every boundary case (PEC walls, CPML slabs,
 // periodic test mode) and the antenna soft source. Shared by the split
-// kernels and the LDS-tiled fused kernel so both compute bit-identical
-// values for a cell.
+// kernels and the batched kernels so both compute bit-identical values for
+// a cell.
 #pragma once
 
 #include "kernels_common.hpp"
@@ -124,6 +124,98 @@ __device__ __forceinline__ void h_cell(const Problem& p, int par, int i, int j, 
         hy += cmul_re(a[HY], qt1);
         hz += cmul_re(a[HZ], qt0);
     }
+}
+
+// E update of cell (i, j, k) of parity par -> par ^ 1 with its neighbour
+// loads, the E source at step n and the plane accumulation selected by
+// diag_mask. Returns |E^{n+1}|² at the cell (for the energy).
+__device__ __forceinline__ double e_point(const Problem& p, long long n, int par, int i, int j,
+                                          int k, int diag_mask) {
+    auto fo = [&](int c) -> const float* { return fptr(p, par, c); };
+    auto fn = [&](int c) -> float* { return fptr(p, par ^ 1, c); };
+    const bool per = p.periodic != 0;
+    const int km = k == 0 ? p.nz - 1 : k - 1;
+    int im = i - 1, jm = j - 1;
+    const bool has_im = im >= 0 || per, has_jm = jm >= 0 || per;
+    if (im < 0) im += p.nx;
+    if (jm < 0) jm += p.ny;
+    const size_t row = ((size_t)k * p.ny + j) * p.pitch;
+    const size_t row_jm = ((size_t)k * p.ny + jm) * p.pitch;
+    const size_t row_km = ((size_t)km * p.ny + j) * p.pitch;
+    const size_t id = row + i;
+    HNbr h;
+    h.hx = fo(HX)[id];
+    h.hy = fo(HY)[id];
+    h.hz = fo(HZ)[id];
+    h.hz_im = has_im ? fo(HZ)[row + im] : 0.f;
+    h.hy_im = has_im ? fo(HY)[row + im] : 0.f;
+    h.hz_jm = has_jm ? fo(HZ)[row_jm + i] : 0.f;
+    h.hx_jm = has_jm ? fo(HX)[row_jm + i] : 0.f;
+    h.hy_km = fo(HY)[row_km + i];
+    h.hx_km = fo(HX)[row_km + i];
+    float ex = fo(EX)[id], ey = fo(EY)[id], ez = fo(EZ)[id];
+    const int slot = p.colmap ? p.colmap[(size_t)j * p.nx + i] : -1;
+    float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
+    if (slot >= 0) {
+        const float2 t = p.tE[n];
+        pt0 = cmul(p.zph[2 * k], t);
+        pt1 = cmul(p.zph[2 * k + 1], t);
+    }
+    e_cell(p, par, i, j, k, h, ex, ey, ez, slot, pt0, pt1, true);
+    fn(EX)[id] = ex;
+    fn(EY)[id] = ey;
+    fn(EZ)[id] = ez;
+    if (k == p.plane && diag_mask) {
+        const size_t pl = (size_t)j * p.nx + i, ps = (size_t)p.nx * p.ny;
+        if (diag_mask & FDTD_DIAG_EX2) p.fl[pl] += (double)ex * ex;
+        if (diag_mask & FDTD_DIAG_EY2) p.fl[ps + pl] += (double)ey * ey;
+        if (diag_mask & FDTD_DIAG_EZ2) p.fl[2 * ps + pl] += (double)ez * ez;
+    }
+    if (k == p.plane && p.rec) p.rec[(size_t)(n - p.rec_begin) * p.nx * p.ny + (size_t)j * p.nx + i] = ey;
+    return (double)ex * ex + (double)ey * ey + (double)ez * ez;
+}
+
+// H update of cell (i, j, k): H of parity par and E^{n+1} of parity par ^ 1
+// -> H of parity par ^ 1, with the H source at step n. Returns
+// H^{n+1/2}·H^{n+3/2} at the cell (for the energy).
+__device__ __forceinline__ double h_point(const Problem& p, long long n, int par, int i, int j,
+                                          int k) {
+    auto fo = [&](int c) -> const float* { return fptr(p, par, c); };
+    auto fn = [&](int c) -> float* { return fptr(p, par ^ 1, c); };   // E^{n+1} is here
+    const bool per = p.periodic != 0;
+    const int kp = k + 1 == p.nz ? 0 : k + 1;
+    int ip = i + 1, jp = j + 1;
+    const bool has_ip = ip < p.nx || per, has_jp = jp < p.ny || per;
+    if (ip >= p.nx) ip -= p.nx;
+    if (jp >= p.ny) jp -= p.ny;
+    const size_t row = ((size_t)k * p.ny + j) * p.pitch;
+    const size_t row_jp = ((size_t)k * p.ny + jp) * p.pitch;
+    const size_t row_kp = ((size_t)kp * p.ny + j) * p.pitch;
+    const size_t id = row + i;
+    ENbr e;
+    e.ex = fn(EX)[id];
+    e.ey = fn(EY)[id];
+    e.ez = fn(EZ)[id];
+    e.ey_ip = has_ip ? fn(EY)[row + ip] : 0.f;
+    e.ez_ip = has_ip ? fn(EZ)[row + ip] : 0.f;
+    e.ex_jp = has_jp ? fn(EX)[row_jp + i] : 0.f;
+    e.ez_jp = has_jp ? fn(EZ)[row_jp + i] : 0.f;
+    e.ex_kp = fn(EX)[row_kp + i];
+    e.ey_kp = fn(EY)[row_kp + i];
+    const float hx0 = fo(HX)[id], hy0 = fo(HY)[id], hz0 = fo(HZ)[id];
+    float hx = hx0, hy = hy0, hz = hz0;
+    const int slot = p.colmap ? p.colmap[(size_t)j * p.nx + i] : -1;
+    float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
+    if (slot >= 0) {
+        const float2 t = p.tH[n];
+        qt0 = cmul(p.zph[2 * k], t);
+        qt1 = cmul(p.zph[2 * k + 1], t);
+    }
+    h_cell(p, par, i, j, k, e, hx, hy, hz, slot, qt0, qt1);
+    fn(HX)[id] = hx;
+    fn(HY)[id] = hy;
+    fn(HZ)[id] = hz;
+    return (double)hx0 * hx + (double)hy0 * hy + (double)hz0 * hz;
 }
 
 }  // namespace bfdtd

@@ -48,9 +48,22 @@ class Solver:
         if rc != L.OK:
             raise L.FdtdError(rc, self._lib.fdtd_last_error(None).decode())
         self._ctx = ctx
+        self._owned = True
         self.nx, self.ny, self.nz = nx, ny, nz
         self.npml = cpml_cells if bc == L.BC_CPML else 0
         self.dx, self.dy, self.dz = dx, dy, dz
+
+    @classmethod
+    def _borrow(cls, ctx, nx, ny, nz, npml, dx, dy, dz):
+        """Handle of a context owned elsewhere (a batch instance); close()
+        leaves it alone."""
+        s = cls.__new__(cls)
+        s._lib = L.load()
+        s._ctx = ctypes.c_void_p(ctx)
+        s._owned = False
+        s.nx, s.ny, s.nz, s.npml = nx, ny, nz, npml
+        s.dx, s.dy, s.dz = dx, dy, dz
+        return s
 
     # -- construction from a shared workload description ------------------
     @classmethod
@@ -71,7 +84,7 @@ class Solver:
 
     # -- API --------------------------------------------------------------
     def close(self):
-        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+        if getattr(self, "_ctx", None) is not None and self._ctx.value and self._owned:
             self._lib.fdtd_destroy(self._ctx)
         self._ctx = None
 

@@ -107,6 +107,23 @@ def config3_instances(seed=1, count=64):
     return out
 
 
+def batch_small(seed=3, count=5):
+    """Small uneven instances for batch parity (the config-3 recipe scaled
+    down): nx = ny ~ U{40..72}, nz_hint ~ U{12..20}, θ ~ {10,15,20,25,30}°,
+    m ~ U{0..3}; Δx = λ/16, 8-cell CPML, R_B = 0.8 (nx/2 - 8) Δx, 2-period
+    ramp, 45 steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        nx = int(rng.integers(40, 73))
+        nzh = int(rng.integers(12, 21))
+        th = float(rng.choice([10.0, 15.0, 20.0, 25.0, 30.0]))
+        m = int(rng.integers(0, 4))
+        out.append(Workload(f"b_small{q}_{nx}_m{m}", nx, nx, nzh, 16.0, th, m,
+                            0.8 * (nx / 2 - 8), 2.0, 8, 45, ramp_periods=2.0))
+    return out
+
+
 def config4():
     """192×192×64 (z fitted), Δx = λ/20, θ = 12°, m = 0, annulus 64Δx, 1500 steps,
     checkpoints every 100 steps, 256 sector weights, 10-period ramp."""
