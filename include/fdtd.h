@@ -240,6 +240,72 @@ int fdtd_profile_enable(fdtd_ctx *ctx, int32_t on);
 /* Copy up to max entries; *count receives the number of kernel names. */
 int fdtd_profile_read(fdtd_ctx *ctx, fdtd_kernel_profile *out, int32_t max, int32_t *count);
 
+/* ---- adjoint: gradient of an intensity loss w.r.t. the sector weights ----
+ * The scheme is linear in (E, H̃, ψ) plus an additive source, so reverse-
+ * mode differentiation is the transposed step run backwards in time: for a
+ * forward curl term ψ' = bψ + cΔ, u' = u + σ S_d((1/κ)Δ + ψ'), the transpose
+ * is μ = σ S_d λ_u', λ_Δ = (1/κ + c)μ + cλ_ψ', λ_ψ = b(μ + λ_ψ'), and the
+ * differenced field receives the transposed difference of λ_Δ (PEC-held
+ * components contribute nothing). The loss L(Ī) depends on the window mean
+ * Ī of E_y² on one plane (§5 intensity); ∂L/∂Ī comes from the caller. The
+ * gradient with respect to a sector weight w_s = a_s e^{iφ_s} (set with
+ * fdtd_set_injector / fdtd_set_sector_weights, §4 amplitudes) is
+ *   ∂L/∂a_s = Σ_{points of s} Re{e^{iφ_s} Ã G},  ∂L/∂φ_s = -Σ Im{w_s Ã G},
+ *   G = Σ_n T(t) Σ_k λ(k) e^{iβ z(k)}  (T the time factor of that half step).
+ * The forward run stores the full state every checkpoint_every steps; the
+ * reverse sweep regenerates, segment by segment from those checkpoints, the
+ * E_y planes the loss needs, so only one segment of planes is held. */
+typedef struct fdtd_adjoint fdtd_adjoint;
+
+typedef struct fdtd_adjoint_info {
+    int32_t checkpoint_every;
+    int32_t checkpoints;         /* state snapshots held                        */
+    int32_t antenna_columns;     /* slots of the per-point correlations G       */
+    int32_t reserved;
+    int64_t forward_steps;       /* steps of the last fdtd_adjoint_forward      */
+    int64_t recompute_steps;     /* forward steps redone by the last backward   */
+    int64_t device_bytes;        /* λ state, checkpoints, plane records, G      */
+} fdtd_adjoint_info;
+
+/* Attach an adjoint to a forward context (which it borrows: destroy the
+ * adjoint first). Allocates λ (fields, CPML memories) and one segment of
+ * plane records. checkpoint_every >= 1. */
+int fdtd_adjoint_create(fdtd_ctx *fwd, int32_t checkpoint_every, fdtd_adjoint **out);
+
+/* Free the adjoint's device memory. NULL-safe. */
+int fdtd_adjoint_destroy(fdtd_adjoint *a);
+
+/* Message of the last failure on a (or of the last failed create). */
+const char *fdtd_adjoint_last_error(const fdtd_adjoint *a);
+
+/* Reset the forward context and run nsteps steps from zero fields with
+ * Ī = window mean of E_y² on plane k_plane over steps >= window_begin
+ * (fdtd_fluence(fwd, FDTD_DIAG_EY2) reads it), storing a checkpoint every
+ * checkpoint_every steps. Requires an injector. */
+int fdtd_adjoint_forward(fdtd_adjoint *a, int64_t nsteps, int32_t k_plane, int64_t window_begin);
+
+/* Reverse sweep for ∂L/∂Ī = dl_dI[ny*nx] (host, x fastest; n = ny*nx):
+ * writes ∂L/∂a_s and ∂L/∂φ_s of the n_sectors sector weights to
+ * grad_amp / grad_phase. Synchronises. The forward context is left at the
+ * end of the last recomputed segment (its fluence sums are untouched). */
+int fdtd_adjoint_backward(fdtd_adjoint *a, const float *dl_dI, int64_t n, int32_t n_sectors,
+                          double *grad_amp, double *grad_phase);
+
+/* Per-point correlations G of the last backward: [slot][component][re, im]
+ * (n = 12 * antenna_columns doubles; slots in the antenna's column order,
+ * components Ex, Ey, Ez, Hx, Hy, Hz). */
+int fdtd_adjoint_source_correlation(fdtd_adjoint *a, double *host, int64_t n);
+
+/* nsteps source-free transposed steps applied to the λ state as it is (for
+ * transposition checks). */
+int fdtd_adjoint_transpose(fdtd_adjoint *a, int64_t nsteps);
+
+/* λ arrays, same ids, host layouts and sizes as fdtd_get_state. */
+int fdtd_adjoint_get_state(fdtd_adjoint *a, int32_t which, float *host, int64_t n);
+int fdtd_adjoint_set_state(fdtd_adjoint *a, int32_t which, const float *host, int64_t n);
+
+int fdtd_adjoint_get_info(const fdtd_adjoint *a, fdtd_adjoint_info *out);
+
 /* ---- batch: many independent instances advanced together -----------------
  * A batch owns `count` solver contexts of uneven grid size, cone angle and
  * order (each made as by fdtd_create with FDTD_KERNEL_SPLIT on the batch's

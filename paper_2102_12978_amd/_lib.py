@@ -63,7 +63,15 @@ class BatchInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+class AdjointInfo(ctypes.Structure):
+    _fields_ = [("checkpoint_every", ctypes.c_int32), ("checkpoints", ctypes.c_int32),
+                ("antenna_columns", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("forward_steps", ctypes.c_int64), ("recompute_steps", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+
 _CTX = ctypes.c_void_p
+_ADJ = ctypes.c_void_p
 _BATCH = ctypes.c_void_p
 _I32P = ctypes.POINTER(ctypes.c_int32)
 _SIGS = {
@@ -93,6 +101,18 @@ _SIGS = {
     "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
+    "fdtd_adjoint_create": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(_ADJ)]),
+    "fdtd_adjoint_destroy": (ctypes.c_int, [_ADJ]),
+    "fdtd_adjoint_last_error": (ctypes.c_char_p, [_ADJ]),
+    "fdtd_adjoint_forward": (ctypes.c_int, [_ADJ, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.c_int64]),
+    "fdtd_adjoint_backward": (ctypes.c_int, [_ADJ, c_float_p, ctypes.c_int64, ctypes.c_int32,
+                                             c_double_p, c_double_p]),
+    "fdtd_adjoint_source_correlation": (ctypes.c_int, [_ADJ, c_double_p, ctypes.c_int64]),
+    "fdtd_adjoint_transpose": (ctypes.c_int, [_ADJ, ctypes.c_int64]),
+    "fdtd_adjoint_get_state": (ctypes.c_int, [_ADJ, ctypes.c_int32, c_float_p, ctypes.c_int64]),
+    "fdtd_adjoint_set_state": (ctypes.c_int, [_ADJ, ctypes.c_int32, c_float_p, ctypes.c_int64]),
+    "fdtd_adjoint_get_info": (ctypes.c_int, [_ADJ, ctypes.POINTER(AdjointInfo)]),
     "fdtd_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Grid),
                                          ctypes.POINTER(Injector), ctypes.c_void_p,
                                          ctypes.POINTER(_BATCH)]),

@@ -37,45 +37,6 @@ bool psi_is_x(int which) {
            which == FDTD_PSI_HZX;
 }
 
-// A fused step: the interior kernel, then the split kernels on the frame
-// around it (the whole grid when there is no interior or for the split
-// kernel choice).
-Frame interior_of(const fdtd_ctx* c) {
-    if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0};
-    return fused_interior_rect(c->p, c->rows);
-}
-
-int interior_partials(const fdtd_ctx* c) {
-    return c->kernel == FDTD_KERNEL_SPLIT ? 0 : fused_interior_tiles(c->p, c->rows, c->zchunk);
-}
-
-int partial_count(const fdtd_ctx* c) {
-    return interior_partials(c) + split_partial_count(c->p, interior_of(c));
-}
-
-void ensure_partials(fdtd_ctx* c) {
-    int need_n = std::max(1, partial_count(c));
-    if (need_n <= c->epart_cap) return;
-    check(hipStreamSynchronize(c->stream), "sync");
-    dfree(c, c->epart);
-    c->epart = dalloc<double>(c, need_n);
-    c->epart_cap = need_n;
-}
-
-hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, int parity,
-                       double* epart) {
-    const Frame fr = interior_of(c);
-    int off = 0;
-    if (fr.x1 > fr.x0) {
-        hipError_t e = launch_fused_interior(q, n, parity, c->rows, c->zchunk, epart, c->stream,
-                                             c->timer);
-        if (e != hipSuccess) return e;
-        off = interior_partials(c);
-    }
-    return launch_split_frame(q, n, parity, fr, epart ? epart + off : nullptr, c->stream,
-                              c->timer);
-}
-
 void launch_one(fdtd_ctx* c, long long n) {
     Problem q = c->p;
     const bool in_window = c->plane >= 0 && n >= c->wbegin;

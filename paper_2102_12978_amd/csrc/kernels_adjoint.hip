@@ -1,0 +1,254 @@
+// Transposed Yee step (reverse-mode differentiation of the linear scheme).
+//
+// The forward step maps x = (E, H̃, ψ_E, ψ_H) to F x + s(t) with the antenna
+// source s independent of x. Its transpose is taken term by term. For a curl
+// term of the forward update
+//     ψ' = b ψ + c Δ,   u' = u + σ S_d ((1/κ) Δ + ψ'),   Δ = D v
+// (D a backward difference for the E part, a forward one for the H part,
+// b = c = 0 and 1/κ = 1 outside the CPML slabs), the transpose with
+// adjoint variables λ reads
+//     μ = σ S_d λ_u',   λ_Δ = (1/κ + c) μ + c λ_ψ',   λ_ψ = b (μ + λ_ψ'),
+//     λ_u = λ_u',       λ_v += Dᵀ λ_Δ = -D_f λ_Δ (E part) or -D_b λ_Δ (H part).
+// E components held by the PEC walls are not updated forward, so their μ is
+// zero and their λ_ψ passes through unchanged.
+//
+// The reverse step undoes the H part first, then the E part. Each kernel
+// updates the λ of the differenced fields in place (a cell only reads λ of
+// the other family and the old ψ) and writes the new λ_ψ to the other
+// parity. One thread per cell; grid (columns / 256, nz).
+#include <hip/hip_runtime.h>
+
+#include "kernels_common.hpp"
+
+namespace bfdtd {
+
+namespace {
+
+constexpr int BT = 256;
+
+struct Lam {
+    const Problem& p;
+    int par, i, j, k;
+    __device__ float* f(int c) const { return p.fbase[0] + c * p.fstride; }
+    __device__ size_t at(int ii, int jj, int kk) const {
+        return ((size_t)kk * p.ny + jj) * p.pitch + ii;
+    }
+    __device__ float v(int c, int ii, int jj, int kk) const { return f(c)[at(ii, jj, kk)]; }
+    __device__ const float* psi_old(int q) const { return pptr(p, par, q); }
+    __device__ float* psi_new(int q) const { return pptr(p, par ^ 1, q); }
+};
+
+// ---- H part transposed: λ_E += -D_b λ_Δ of the H terms ------------------
+// λ_Δ of the H term (h_comp, d = x) at column ii of row j, plane k.
+__device__ __forceinline__ float dh_x(const Lam& L, int hc, int q, float sign, int ii) {
+    const Problem& p = L.p;
+    if (ii < 0) {
+        if (!p.periodic) return 0.f;
+        ii += p.nx;
+    }
+    const float mu = sign * p.sx * L.v(hc, ii, L.j, L.k);
+    const int xs = slab_index(ii, p.nx, p.npml);
+    if (xs < 0) return mu;
+    const float c = cx_tab(p, T_HC)[ii], kinv = cx_tab(p, T_HK)[ii];
+    return (kinv + c) * mu + c * L.psi_old(q)[psix_at(p, L.k, L.j, xs)];
+}
+
+__device__ __forceinline__ float dh_y(const Lam& L, int hc, int q, float sign, int jj) {
+    const Problem& p = L.p;
+    if (jj < 0) {
+        if (!p.periodic) return 0.f;
+        jj += p.ny;
+    }
+    const float mu = sign * p.sy * L.v(hc, L.i, jj, L.k);
+    const int ys = slab_index(jj, p.ny, p.npml);
+    if (ys < 0) return mu;
+    const float c = cy_tab(p, T_HC)[jj], kinv = cy_tab(p, T_HK)[jj];
+    return (kinv + c) * mu + c * L.psi_old(q)[psiy_at(p, L.k, ys, L.i)];
+}
+
+__device__ __forceinline__ float dh_z(const Lam& L, int hc, float sign, int kk) {
+    const Problem& p = L.p;
+    if (kk < 0) kk += p.nz;
+    return sign * p.sz * L.v(hc, L.i, L.j, kk);
+}
+
+__global__ void __launch_bounds__(BT) adj_h_kernel(Problem p, int par) {
+    const int col = blockIdx.x * BT + threadIdx.x;
+    if (col >= p.nx * p.ny) return;
+    const Lam L{p, par, col % p.nx, col / p.nx, (int)blockIdx.y};
+    const int i = L.i, j = L.j, k = L.k;
+    const size_t id = L.at(i, j, k);
+    // H terms: hx: (ez, y, -1, ψ_hxy) (ey, z, +1); hy: (ex, z, -1) (ez, x, +1, ψ_hyx);
+    //          hz: (ey, x, -1, ψ_hzx) (ex, y, +1, ψ_hzy)
+    const float gx = -(dh_z(L, HY, -1.f, k) - dh_z(L, HY, -1.f, k - 1)) -
+                     (dh_y(L, HZ, P_HZY, 1.f, j) - dh_y(L, HZ, P_HZY, 1.f, j - 1));
+    const float gy = -(dh_z(L, HX, 1.f, k) - dh_z(L, HX, 1.f, k - 1)) -
+                     (dh_x(L, HZ, P_HZX, -1.f, i) - dh_x(L, HZ, P_HZX, -1.f, i - 1));
+    const float gz = -(dh_y(L, HX, P_HXY, -1.f, j) - dh_y(L, HX, P_HXY, -1.f, j - 1)) -
+                     (dh_x(L, HY, P_HYX, 1.f, i) - dh_x(L, HY, P_HYX, 1.f, i - 1));
+    L.f(EX)[id] += gx;
+    L.f(EY)[id] += gy;
+    L.f(EZ)[id] += gz;
+    // λ_ψ of the H memories at this cell
+    const int xs = slab_index(i, p.nx, p.npml), ys = slab_index(j, p.ny, p.npml);
+    if (xs >= 0) {
+        const float b = cx_tab(p, T_HB)[i];
+        const size_t q = psix_at(p, k, j, xs);
+        L.psi_new(P_HYX)[q] = b * (p.sx * L.v(HY, i, j, k) + L.psi_old(P_HYX)[q]);
+        L.psi_new(P_HZX)[q] = b * (-p.sx * L.v(HZ, i, j, k) + L.psi_old(P_HZX)[q]);
+    }
+    if (ys >= 0) {
+        const float b = cy_tab(p, T_HB)[j];
+        const size_t q = psiy_at(p, k, ys, i);
+        L.psi_new(P_HXY)[q] = b * (-p.sy * L.v(HX, i, j, k) + L.psi_old(P_HXY)[q]);
+        L.psi_new(P_HZY)[q] = b * (p.sy * L.v(HZ, i, j, k) + L.psi_old(P_HZY)[q]);
+    }
+}
+
+// ---- E part transposed: λ_H += -D_f λ_Δ of the E terms ------------------
+// E components updated at (ii, jj): E_y and E_z are held on the x = 0 wall,
+// E_x and E_z on the y = 0 wall.
+__device__ __forceinline__ bool upd_e(const Problem& p, int ec, int ii, int jj) {
+    if (p.periodic) return true;
+    const bool hx = ii == 0, hy = jj == 0;
+    if (ec == EX) return !hy;
+    if (ec == EY) return !hx;
+    return !hx && !hy;
+}
+
+__device__ __forceinline__ float de_x(const Lam& L, int ec, int q, float sign, int ii) {
+    const Problem& p = L.p;
+    if (ii >= p.nx) {
+        if (!p.periodic) return 0.f;
+        ii -= p.nx;
+    }
+    if (!upd_e(p, ec, ii, L.j)) return 0.f;
+    const float mu = sign * p.sx * L.v(ec, ii, L.j, L.k);
+    const int xs = slab_index(ii, p.nx, p.npml);
+    if (xs < 0) return mu;
+    const float c = cx_tab(p, T_EC)[ii], kinv = cx_tab(p, T_EK)[ii];
+    return (kinv + c) * mu + c * L.psi_old(q)[psix_at(p, L.k, L.j, xs)];
+}
+
+__device__ __forceinline__ float de_y(const Lam& L, int ec, int q, float sign, int jj) {
+    const Problem& p = L.p;
+    if (jj >= p.ny) {
+        if (!p.periodic) return 0.f;
+        jj -= p.ny;
+    }
+    if (!upd_e(p, ec, L.i, jj)) return 0.f;
+    const float mu = sign * p.sy * L.v(ec, L.i, jj, L.k);
+    const int ys = slab_index(jj, p.ny, p.npml);
+    if (ys < 0) return mu;
+    const float c = cy_tab(p, T_EC)[jj], kinv = cy_tab(p, T_EK)[jj];
+    return (kinv + c) * mu + c * L.psi_old(q)[psiy_at(p, L.k, ys, L.i)];
+}
+
+__device__ __forceinline__ float de_z(const Lam& L, int ec, float sign, int kk) {
+    const Problem& p = L.p;
+    if (kk >= p.nz) kk -= p.nz;
+    if (!upd_e(p, ec, L.i, L.j)) return 0.f;
+    return sign * p.sz * L.v(ec, L.i, L.j, kk);
+}
+
+__global__ void __launch_bounds__(BT) adj_e_kernel(Problem p, int par) {
+    const int col = blockIdx.x * BT + threadIdx.x;
+    if (col >= p.nx * p.ny) return;
+    const Lam L{p, par, col % p.nx, col / p.nx, (int)blockIdx.y};
+    const int i = L.i, j = L.j, k = L.k;
+    const size_t id = L.at(i, j, k);
+    // E terms: ex: (hz, y, +1, ψ_exy) (hy, z, -1); ey: (hx, z, +1) (hz, x, -1, ψ_eyx);
+    //          ez: (hy, x, +1, ψ_ezx) (hx, y, -1, ψ_ezy)
+    const float gx = -(de_z(L, EY, 1.f, k + 1) - de_z(L, EY, 1.f, k)) -
+                     (de_y(L, EZ, P_EZY, -1.f, j + 1) - de_y(L, EZ, P_EZY, -1.f, j));
+    const float gy = -(de_z(L, EX, -1.f, k + 1) - de_z(L, EX, -1.f, k)) -
+                     (de_x(L, EZ, P_EZX, 1.f, i + 1) - de_x(L, EZ, P_EZX, 1.f, i));
+    const float gz = -(de_y(L, EX, P_EXY, 1.f, j + 1) - de_y(L, EX, P_EXY, 1.f, j)) -
+                     (de_x(L, EY, P_EYX, -1.f, i + 1) - de_x(L, EY, P_EYX, -1.f, i));
+    L.f(HX)[id] += gx;
+    L.f(HY)[id] += gy;
+    L.f(HZ)[id] += gz;
+    const int xs = slab_index(i, p.nx, p.npml), ys = slab_index(j, p.ny, p.npml);
+    if (xs >= 0) {
+        const float b = cx_tab(p, T_EB)[i];
+        const size_t q = psix_at(p, k, j, xs);
+        const float oy = L.psi_old(P_EYX)[q], oz = L.psi_old(P_EZX)[q];
+        L.psi_new(P_EYX)[q] = upd_e(p, EY, i, j) ? b * (-p.sx * L.v(EY, i, j, k) + oy) : oy;
+        L.psi_new(P_EZX)[q] = upd_e(p, EZ, i, j) ? b * (p.sx * L.v(EZ, i, j, k) + oz) : oz;
+    }
+    if (ys >= 0) {
+        const float b = cy_tab(p, T_EB)[j];
+        const size_t q = psiy_at(p, k, ys, i);
+        const float ox = L.psi_old(P_EXY)[q], oz = L.psi_old(P_EZY)[q];
+        L.psi_new(P_EXY)[q] = upd_e(p, EX, i, j) ? b * (p.sy * L.v(EX, i, j, k) + ox) : ox;
+        L.psi_new(P_EZY)[q] = upd_e(p, EZ, i, j) ? b * (-p.sy * L.v(EZ, i, j, k) + oz) : oz;
+    }
+}
+
+// ∂L/∂E_y^{n+1} on the intensity plane: λ_Ey += coef · g · E_y (the
+// intensity is the window mean of E_y², g = ∂L/∂Ī).
+__global__ void __launch_bounds__(BT) adj_inject_kernel(Problem p, const float* g, const float* ey,
+                                                        float coef) {
+    const int col = blockIdx.x * BT + threadIdx.x;
+    if (col >= p.nx * p.ny) return;
+    const int i = col % p.nx, j = col / p.nx;
+    float* f = p.fbase[0] + EY * p.fstride;
+    f[((size_t)p.plane * p.ny + j) * p.pitch + i] += coef * g[col] * ey[col];
+}
+
+// G_c(slot) += T(t) Σ_k λ_c(k, j, i) e^{iβ z_c(k)} for one half step: three
+// components (first = EX or HX) of every antenna column, in double.
+__global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, const int* slot_i,
+                                                      const int* slot_j, int nslots, int first,
+                                                      float2 t, double2* G) {
+    const int tid = blockIdx.x * BT + threadIdx.x;
+    if (tid >= nslots * 3) return;
+    const int s = tid / 3, c = first + tid % 3;
+    const int i = slot_i[s], j = slot_j[s];
+    // integer-plane components: E_x, E_y, H_z; half-plane: E_z, H_x, H_y
+    const int half = (c == EZ || c == HX || c == HY) ? 1 : 0;
+    const float* f = p.fbase[0] + c * p.fstride + (size_t)j * p.pitch + i;
+    const size_t plane = (size_t)p.ny * p.pitch;
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < p.nz; ++k) {
+        const double l = f[k * plane];
+        const float2 z = p.zph[2 * k + half];
+        re += l * z.x;
+        im += l * z.y;
+    }
+    double2 g = G[(size_t)s * 6 + c];
+    g.x += re * t.x - im * t.y;
+    g.y += re * t.y + im * t.x;
+    G[(size_t)s * 6 + c] = g;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_h(const Problem& lam, int par, hipStream_t s) {
+    dim3 grid((unsigned)((lam.nx * lam.ny + BT - 1) / BT), lam.nz);
+    hipLaunchKernelGGL(adj_h_kernel, grid, dim3(BT), 0, s, lam, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_e(const Problem& lam, int par, hipStream_t s) {
+    dim3 grid((unsigned)((lam.nx * lam.ny + BT - 1) / BT), lam.nz);
+    hipLaunchKernelGGL(adj_e_kernel, grid, dim3(BT), 0, s, lam, par);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_inject(const Problem& lam, const float* g, const float* ey, float coef,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(adj_inject_kernel, dim3((lam.nx * lam.ny + BT - 1) / BT), dim3(BT), 0, s,
+                       lam, g, ey, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gacc(const Problem& lam, const int* slot_i, const int* slot_j,
+                               int nslots, int first, float2 t, double2* G, hipStream_t s) {
+    if (nslots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(adj_gacc_kernel, dim3((nslots * 3 + BT - 1) / BT), dim3(BT), 0, s, lam,
+                       slot_i, slot_j, nslots, first, t, G);
+    return hipGetLastError();
+}
+
+}  // namespace bfdtd

@@ -132,6 +132,15 @@ def config4():
                     extra={"checkpoint_every": 100, "sectors": 256})
 
 
+def config4_tiny():
+    """24×24×(24 hint) copy of config 4 for the autograd reference: Δx = λ/20,
+    θ = 12°, m = 0, 4-cell CPML, R_B = 0.8 (12 - 4) Δx, δs = 2Δx, 300 steps,
+    2.5-period ramp, window = last 5 periods, the same 256 seed-2 sector
+    weights."""
+    return Workload("c4tiny_24_theta12_m0", 24, 24, 24, 20.0, 12.0, 0, 6.4, 2.0, 4, 300,
+                    ramp_periods=2.5, extra={"checkpoint_every": 100, "sectors": 256})
+
+
 def config4_sector_params(seed=2, sectors=256):
     """Initial sector amplitudes a = 1 + 0.05 N(0,1) and phases φ = 0.1 N(0,1)
     (amplitudes drawn first)."""

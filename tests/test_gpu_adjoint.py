@@ -1,0 +1,266 @@
+"""The transposed step and the sector gradient on the GPU.
+
+* Transposition: ⟨F x, y⟩ = ⟨x, Fᵀ y⟩ with the GPU forward step F and the
+  GPU transposed step, random x and y including CPML memories and wall
+  values (FP32: relative gap ≤ 1e-5), on the split path and on a grid where
+  the fused interior kernel runs.
+* The transposed step against the oracle's (FP64) from the same λ, element
+  by element (relative L2 ≤ 1e-4).
+* The sector gradient (forward with checkpoints, reverse sweep with
+  recomputation) against the oracle's reverse-mode gradient (≤ 1e-3 of the
+  largest component), and the autograd.Function end to end.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import adjoint as OA
+from oracle import problem as P
+from oracle import yee as Y
+from paper_2102_12978_amd import _lib as L
+from paper_2102_12978_amd import workloads as W
+from paper_2102_12978_amd.adjoint import Adjoint, SectorIntensity, SectorSensitivity
+from tests import cases
+from tests import gpu_cases as GC
+
+pytestmark = pytest.mark.gpu
+
+IDS = list(range(6)) + list(GC.PSI)
+
+
+def _shapes(s):
+    return {q: s.state_shape(q) for q in IDS if q < 6 or s.npml > 0}
+
+
+def _dot(a, b):
+    return sum(float(np.dot(a[q].astype(np.float64).ravel(), b[q].astype(np.float64).ravel()))
+               for q in a)
+
+
+def _small(bc=L.BC_CPML):
+    w = W.Workload("adj_40x36", 40, 36, 12, 14.0, 25.0, 1, 12.0, 2.0, 6 if bc == L.BC_CPML else 0,
+                   10, bc=bc)
+    return w
+
+
+@pytest.mark.parametrize("bc", [L.BC_PERIODIC, L.BC_PEC, L.BC_CPML])
+@pytest.mark.parametrize("nsteps", [1, 3])
+def test_dot_product_identity(bc, nsteps):
+    w = _small(bc)
+    s = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT, bc=bc, inject=False)
+    adj = Adjoint(s)
+    rng = np.random.default_rng(7 + bc + nsteps)
+    sh = _shapes(s)
+    x = {q: rng.standard_normal(v).astype(np.float32) for q, v in sh.items()}
+    y = {q: rng.standard_normal(v).astype(np.float32) for q, v in sh.items()}
+    for q, v in x.items():
+        s.set_state(q, v)
+    s.step(nsteps)
+    fx = {q: s.get_state(q) for q in sh}
+    for q, v in y.items():
+        adj.set_state(q, v)
+    adj.transpose(nsteps)
+    fty = {q: adj.get_state(q) for q in sh}
+    lhs, rhs = _dot(fx, y), _dot(x, fty)
+    gap = abs(lhs - rhs) / (abs(lhs) + abs(rhs))
+    print(f"  <Fx,y> = {lhs:.8e}, <x,F^T y> = {rhs:.8e}, gap {gap:.1e}", flush=True)
+    assert gap < 1e-5
+    adj.close()
+    s.close()
+
+
+def test_dot_product_identity_fused_grid():
+    """parity_mid grid: the forward step runs the fused interior kernel."""
+    w = W.parity_mid()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, inject=False)
+    adj = Adjoint(s)
+    rng = np.random.default_rng(11)
+    sh = _shapes(s)
+    x = {q: rng.standard_normal(v).astype(np.float32) for q, v in sh.items()}
+    y = {q: rng.standard_normal(v).astype(np.float32) for q, v in sh.items()}
+    for q, v in x.items():
+        s.set_state(q, v)
+    s.step(2)
+    fx = {q: s.get_state(q) for q in sh}
+    for q, v in y.items():
+        adj.set_state(q, v)
+    adj.transpose(2)
+    fty = {q: adj.get_state(q) for q in sh}
+    lhs, rhs = _dot(fx, y), _dot(x, fty)
+    gap = abs(lhs - rhs) / (abs(lhs) + abs(rhs))
+    print(f"  gap {gap:.1e}", flush=True)
+    assert gap < 1e-5
+    adj.close()
+    s.close()
+
+
+def _slab_to_full(arr, which, npml, nx, ny):
+    if which in (L.PSI_EYX, L.PSI_EZX, L.PSI_HYX, L.PSI_HZX):
+        full = np.zeros((arr.shape[0], ny, nx))
+        full[:, :, :npml] = arr[:, :, :npml]
+        full[:, :, nx - npml:] = arr[:, :, npml:]
+    else:
+        full = np.zeros((arr.shape[0], ny, nx))
+        full[:, :npml, :] = arr[:, :npml, :]
+        full[:, ny - npml:, :] = arr[:, npml:, :]
+    return full
+
+
+def test_transposed_step_matches_oracle():
+    w = _small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT, inject=False)
+    adj = Adjoint(s)
+    g = cases.oracle_grid(w)
+    cp = P.cpml_tables(g)
+    rng = np.random.default_rng(3)
+    lam = Y.zero_state(g)
+    for q, c in enumerate(GC.COMPS):
+        v = rng.standard_normal((g.nz, g.ny, g.nx)).astype(np.float32)
+        adj.set_state(q, v)
+        lam.f[c] = v.astype(np.float64)
+    for q, name in GC.PSI.items():
+        v = rng.standard_normal(s.state_shape(q)).astype(np.float32)
+        adj.set_state(q, v)
+        lam.psi[name] = _slab_to_full(v.astype(np.float64), q, g.npml, g.nx, g.ny)
+    adj.transpose(2)
+    for _ in range(2):
+        OA.adjoint_step(lam, g, cp)
+    rel = GC.rel_l2([adj.get_state(q) for q in range(6)], [lam.f[c] for c in GC.COMPS])
+    prel = GC.rel_l2([adj.get_state(q) for q in GC.PSI],
+                     [GC.psi_slab(lam.psi[n], q, g.npml, g.nx, g.ny) for q, n in GC.PSI.items()])
+    print(f"  lambda rel-L2 fields {rel:.1e}, psi {prel:.1e}", flush=True)
+    assert rel < 1e-4 and prel < 1e-4
+    adj.close()
+    s.close()
+
+
+def _grad_problem():
+    """48×48, θ = 30°, m = 0, 16 sectors with seeded weights, 90 steps,
+    window of the last 30, checkpoints every 25 steps (the window spans two
+    segments, the last one short)."""
+    w = W.Workload("adj_48_m0", 48, 48, 10, 12.0, 30.0, 0, 12.0, 2.0, 6, 90, ramp_periods=2.0,
+                   extra={"sectors": 16, "checkpoint_every": 25})
+    rng = np.random.default_rng(21)
+    amp = 1.0 + 0.05 * rng.standard_normal(16)
+    ph = 0.1 * rng.standard_normal(16)
+    return w, amp, ph
+
+
+def _target(ny, nx):
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.hypot(ii - nx / 2.0, jj + 0.5 - ny / 2.0)
+    return r < 9.0, 1e-3 * np.exp(-(r / 4.0) ** 2)
+
+
+def test_gradient_matches_oracle():
+    w, amp, ph = _grad_problem()
+    sens = SectorSensitivity(w, window_begin=60)
+    ibar = sens.intensity(amp, ph).astype(np.float64)
+    region, target = _target(*ibar.shape)
+    nreg = np.count_nonzero(region)
+    dl = np.where(region, 2.0 * (ibar - target) / nreg, 0.0)
+    ga, gp = sens.backward(dl)
+    inf = sens.adj.info()
+    print(f"  checkpoints {inf.checkpoints}, recomputed steps {inf.recompute_steps}", flush=True)
+    assert inf.checkpoints == 4 and inf.recompute_steps == 40
+    g = cases.oracle_grid(w)
+    inj = cases.oracle_injector(w, amp=amp, phase=ph)
+    loss, ibar_o, ga_o, gp_o, _ = OA.intensity_loss_grad(g, inj, w.steps, sens.plane, 60,
+                                                         target, region)
+    assert GC.rel_l2([ibar], [ibar_o]) < 1e-4
+    scale = max(np.abs(ga_o).max(), np.abs(gp_o).max())
+    err = max(np.abs(ga - ga_o).max(), np.abs(gp - gp_o).max()) / scale
+    print(f"  sector gradient vs oracle: max error {err:.1e} of the largest component",
+          flush=True)
+    assert err < 1e-3
+    # a second backward from the same forward gives the same gradient
+    ga2, gp2 = sens.backward(dl)
+    assert np.array_equal(ga, ga2) and np.array_equal(gp, gp2)
+    sens.close()
+
+
+def test_autograd_function():
+    w, amp, ph = _grad_problem()
+    sens = SectorSensitivity(w, window_begin=60)
+    a = torch.tensor(amp, requires_grad=True)
+    p = torch.tensor(ph, requires_grad=True)
+    ibar = SectorIntensity.apply(a, p, sens)
+    region, target = _target(*ibar.shape)
+    reg = torch.from_numpy(region)
+    loss = ((ibar - torch.from_numpy(target))[reg] ** 2).mean()
+    loss.backward()
+    dl = np.where(region, 2.0 * (ibar.detach().numpy() - target) / region.sum(), 0.0)
+    ga, gp = sens.backward(dl)
+    assert np.allclose(a.grad.numpy(), ga, rtol=1e-6, atol=1e-30)
+    assert np.allclose(p.grad.numpy(), gp, rtol=1e-6, atol=1e-30)
+    sens.close()
+
+
+def _c4_loss_grad(sens, amp, ph, A):
+    from paper_2102_12978_amd.adjoint import central_lobe_target
+    region, j0sq = central_lobe_target(sens)
+    a = torch.tensor(amp, requires_grad=True)
+    p = torch.tensor(ph, requires_grad=True)
+    ibar = SectorIntensity.apply(a, p, sens)
+    reg = torch.from_numpy(region)
+    loss = ((ibar - A * torch.from_numpy(j0sq))[reg] ** 2).mean()
+    loss.backward()
+    return loss.item(), a.grad.numpy(), p.grad.numpy(), region, j0sq
+
+
+def test_torch_reference_24():
+    """24×24×20 copy of the differentiable workload (300 steps, 256 seed-2
+    sector weights, loss against A J_0²): GPU adjoint vs torch.autograd
+    through the pure-PyTorch FP64 forward."""
+    from oracle import torch_ref as T
+    from paper_2102_12978_amd.adjoint import on_axis
+    w = W.config4_tiny()
+    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    sens = SectorSensitivity(w)
+    print(f"[gpu case] {w.name}: {sens.steps} steps, window from {sens.window_begin}", flush=True)
+    A = on_axis(sens.intensity(np.ones(256), np.zeros(256)).astype(np.float64))
+    loss, ga, gp, region, j0sq = _c4_loss_grad(sens, amp, ph, A)
+    g = cases.oracle_grid(w)
+    ref = T.TorchYee(g, cases.oracle_injector(w, amp=amp, phase=ph))
+    a2 = torch.tensor(amp, requires_grad=True)
+    p2 = torch.tensor(ph, requires_grad=True)
+    ib2 = ref.intensity(a2, p2, sens.steps, sens.plane, sens.window_begin)
+    reg = torch.from_numpy(region)
+    loss2 = ((ib2 - A * torch.from_numpy(j0sq))[reg] ** 2).mean()
+    loss2.backward()
+    scale = max(a2.grad.abs().max().item(), p2.grad.abs().max().item())
+    err = max(np.abs(ga - a2.grad.numpy()).max(), np.abs(gp - p2.grad.numpy()).max()) / scale
+    print(f"  loss GPU {loss:.6e} vs torch {loss2.item():.6e}; gradient error {err:.1e}",
+          flush=True)
+    assert abs(loss - loss2.item()) <= 1e-4 * loss2.item()
+    assert err < 1e-3
+    sens.close()
+
+
+def test_c4_gradient_vs_finite_differences():
+    """192×192×61, 1500 steps, checkpoints every 100: adjoint gradients at 8
+    amplitudes and 8 phases (sectors 32 q + 5) against FP64 central
+    differences (h = 1e-3) stored by tests/golden/make_c4_fd.py."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c4_fd_gradient.json")
+    fd = json.load(open(path))
+    w = W.config4()
+    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    sens = SectorSensitivity(w)
+    print(f"[gpu case] {w.name}: {sens.steps} steps, checkpoints every {sens.every}", flush=True)
+    loss, ga, gp, _, _ = _c4_loss_grad(sens, amp, ph, fd["A_on_axis"])
+    inf = sens.adj.info()
+    assert inf.checkpoints == 15 and inf.recompute_steps == 200
+    sec = fd["sectors"]
+    got = np.concatenate([ga[sec], gp[sec]])
+    ref = np.concatenate([fd["grad_amp_fd"], fd["grad_phase_fd"]])
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"  loss {loss:.6e} (FP64 {fd['loss']:.6e}); max gradient error {err:.1e} of the "
+          f"largest; per probe " + ", ".join(f"{x:.1e}" for x in np.abs(got - ref) /
+                                             np.abs(ref)), flush=True)
+    assert abs(loss - fd["loss"]) <= 1e-4 * fd["loss"]
+    assert err < 1e-3
+    sens.close()
