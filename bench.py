@@ -127,6 +127,60 @@ def batch_measure(torch, stream, steps=1000, warmup=20):
     }
 
 
+def adjoint_measure(torch, stream):
+    """Gradient cost on the differentiable workload (192×192×61, 1500 steps,
+    checkpoints every 100, 256 sector weights): forward with checkpoints +
+    reverse sweep, against a plain 1500-step forward of the same problem."""
+    import numpy as np
+    from paper_2102_12978_amd import _lib as L
+    from paper_2102_12978_amd import workloads as W
+    from paper_2102_12978_amd.adjoint import SectorSensitivity, central_lobe_target, on_axis
+    w = W.config4()
+    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    sens = SectorSensitivity(w, stream=stream.cuda_stream)
+    s = sens.solver
+    A = on_axis(sens.intensity(np.ones(256), np.zeros(256)).astype(np.float64))
+    region, j0sq = central_lobe_target(sens)
+    target = A * j0sq
+
+    def plain():
+        s.set_sector_weights(amp, ph)
+        s.reset()
+        s.set_diagnostics(sens.plane, sens.window_begin, L.DIAG_EY2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(sens.steps)
+        ib = s.fluence(L.DIAG_EY2)          # synchronises
+        return time.perf_counter() - t0, ib
+
+    def grad():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ib = sens.intensity(amp, ph).astype(np.float64)
+        dl = np.where(region, 2.0 * (ib - target) / np.count_nonzero(region), 0.0)
+        ga, gp = sens.backward(dl)
+        return time.perf_counter() - t0, ga, gp
+
+    plain()
+    grad()
+    t_plain = min(plain()[0] for _ in range(3))
+    t_grad = min(grad()[0] for _ in range(3))
+    inf = sens.adj.info()
+    cells = s.nx * s.ny * s.nz
+    sens.close()
+    return {
+        "workload": "192x192x64 (z fitted to 61), dx=lambda/20, theta=12deg, order 0, "
+                    "256 sector amplitude/phase weights (seed 2), 1500 steps, checkpoints "
+                    "every 100, loss on the mid-plane window-mean E_y^2",
+        "cells": cells, "steps": sens.steps,
+        "forward_ms": round(1e3 * t_plain, 2),
+        "forward_plus_adjoint_ms": round(1e3 * t_grad, 2),
+        "grad_over_forward": round(t_grad / t_plain, 3),
+        "checkpoints": inf.checkpoints, "recompute_steps": inf.recompute_steps,
+        "adjoint_device_bytes": inf.device_bytes,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +191,7 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="fix the tile rows (skips autotune)")
     ap.add_argument("--zchunk", type=int, default=0, help="z chunk with --rows")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has "
@@ -222,6 +277,10 @@ def main():
         log("[bench] 64-instance batch ...")
         out["batch"] = batch_measure(torch, stream)
         log(f"[bench] batch: {out['batch']['value']} Gcell/s")
+    if not args.no_adjoint:
+        log("[bench] adjoint gradient cost ...")
+        out["adjoint"] = adjoint_measure(torch, stream)
+        log(f"[bench] adjoint: {out['adjoint']}")
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(w)
