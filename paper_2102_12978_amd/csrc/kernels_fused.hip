@@ -10,21 +10,24 @@
 // store covers whole lines) × TY y rows and marches along z over a chunk of
 // planes, keeping two planes of each field in registers.
 //   * x: lane l holds x = x0 + l; x neighbours move between lanes with
-//     cross-lane shuffles. A workgroup holds four x-adjacent wavefronts; the
-//     values their edge lanes need from the neighbouring wavefront (H at
-//     x0-1 for lane 0, E_new at x0+64 for lane 63) pass through a small
-//     double-buffered LDS exchange, one barrier per plane. The outermost
-//     wavefronts of the group load H at x0-1 with single-lane loads and form
-//     E_new at x0+64 from single-lane loads.
+//     cross-lane shuffles. Lane 0 loads H at x0-1 with single-lane loads;
+//     lane 63 forms E_new at x0+64 from single-lane loads of that column.
+//     Wavefronts never wait for each other: there is no barrier, so each
+//     keeps its own loads in flight.
 //   * y: each lane holds rows j0-1 .. j0+TY of H and j0 .. j0+TY of E in
 //     registers; E_new of row j0+TY is recomputed for the H update of the
-//     last owned row.
+//     last owned row. A workgroup stacks four wavefronts of the same x
+//     segment in y, so the halo rows they share are fetched by one CU at
+//     about the same time.
 //   * z: E_new(k+1) is formed from H_old(k+1) and H_old(k), then H_new(k)
 //     from E_new(k) and E_new(k+1); the z index wraps (periodic axis).
 // Addresses are a uniform component base (scalar registers) plus a 32-bit
-// per-lane byte offset. Hardware block b runs on XCD b % 8; the block index
-// is remapped so each XCD receives a contiguous run of tiles and the y-halo
-// rows shared by neighbouring tiles stay in one L2.
+// per-lane byte offset. The new fields are written with non-temporal stores:
+// nothing reads them again in this launch, and keeping them out of the
+// caches leaves room for the halo rows that neighbouring tiles re-read.
+// Hardware block b runs on XCD b % 8; the block index is remapped so each
+// XCD receives a contiguous run of tiles and the y-halo rows shared by
+// neighbouring tiles stay in one L2.
 #include <hip/hip_runtime.h>
 
 #include "kernels_common.hpp"
@@ -33,7 +36,7 @@ namespace bfdtd {
 
 namespace {
 
-constexpr int WAVES = 4;   // x-adjacent wavefronts per workgroup
+constexpr int WAVES = 4;   // wavefronts per workgroup, stacked in y
 constexpr int SEG = 64;    // x cells per wavefront
 
 __device__ __forceinline__ float ldo(const float* base, unsigned boff) {
@@ -41,7 +44,7 @@ __device__ __forceinline__ float ldo(const float* base, unsigned boff) {
 }
 
 __device__ __forceinline__ void sto(float* base, unsigned boff, float v) {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
 }
 
 // Interior geometry: segment s covers x in [x_org + 64 s, x_org + 64 s + 64),
@@ -84,15 +87,6 @@ struct Tile {
     __device__ void st(int c, int kk, int r, float v) const {
         sto(fw[c], (unsigned)kk * pstride + ro[r + 1], v);
     }
-};
-
-// LDS exchange between x-adjacent wavefronts, double-buffered by iteration.
-template <int TY>
-struct Exchange {
-    float hy[2][WAVES][TY + 1];   // H_y at x0+63 of wave w (rows 0..TY)
-    float hz[2][WAVES][TY];       // H_z at x0+63 of wave w (rows 0..TY-1)
-    float ey[2][WAVES][TY];       // E_new_y at x0 of wave w (rows 0..TY-1)
-    float ez[2][WAVES][TY];       // E_new_z at x0 of wave w
 };
 
 // E_new on plane kk, rows 0..TY (ex/ey/ez hold E_old on entry); hx/hy/hz are
@@ -176,75 +170,44 @@ __global__ void __launch_bounds__(64 * WAVES)
 __attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 1)))
 fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_padded,
                       double* epart) {
-    __shared__ Exchange<TY> X;
     // ---- which tile: hardware block b runs on XCD b % 8 ----------------
-    const int ngrp = (I.nseg + WAVES - 1) / WAVES;
+    const int nrq = (I.nrow + WAVES - 1) / WAVES;              // row groups per workgroup
     const int lb = (blockIdx.x % 8) * (nblocks_padded / 8) + blockIdx.x / 8;
-    if (lb >= ngrp * I.nrow * I.ncz) return;                   // whole workgroup
+    if (lb >= I.nseg * nrq * I.ncz) return;                    // whole workgroup
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int grp = lb % ngrp;
-    const int sy = (lb / ngrp) % I.nrow;
-    const int kb = (lb / (ngrp * I.nrow)) * I.cz;
+    const int seg = lb % I.nseg;
+    const int sy = ((lb / I.nseg) % nrq) * WAVES + w;
+    const int kb = (lb / (I.nseg * nrq)) * I.cz;
     const int ke = min(kb + I.cz, p.nz);
-    const int seg = grp * WAVES + w;
-    const bool active = seg < I.nseg;                          // uniform per wave
-    const int seg_last = min(grp * WAVES + WAVES, I.nseg) - 1;
-    const bool left_global = w == 0;                           // H at x0-1 from memory
-    const bool right_global = seg == seg_last;                 // E at x0+64 formed here
+    double* epart_slot = epart ? epart + ((size_t)lb * WAVES + w) : nullptr;
+    if (sy >= I.nrow) {                                        // uniform per wavefront
+        if (epart_slot && (threadIdx.x & 63) == 0) *epart_slot = 0.0;
+        return;
+    }
     const int j0 = I.y_org + sy * TY;
-    const Tile<TY> T(p, par, I.x_org + SEG * (active ? seg : 0), j0);
+    const Tile<TY> T(p, par, I.x_org + SEG * seg, j0);
     const int lane = T.lane;
     const int nz = p.nz, nx = p.nx, ny = p.ny;
     const bool right = lane == 63;
-    double* epart_slot = epart ? epart + ((size_t)lb * WAVES + w) : nullptr;
 
     int slot[TY + 1], slot_h[TY];
 #pragma unroll
-    for (int r = 0; r <= TY; ++r)
-        slot[r] = (p.colmap && active) ? p.colmap[(size_t)(j0 + r) * nx + T.x] : -1;
+    for (int r = 0; r <= TY; ++r) slot[r] = p.colmap ? p.colmap[(size_t)(j0 + r) * nx + T.x] : -1;
 #pragma unroll
     for (int r = 0; r < TY; ++r)
-        slot_h[r] = (p.colmap && active && right && right_global)
-                        ? p.colmap[(size_t)(j0 + r) * nx + T.x + 1] : -1;
+        slot_h[r] = (p.colmap && right) ? p.colmap[(size_t)(j0 + r) * nx + T.x + 1] : -1;
 
     float hcx[TY], hcy[TY + 1], hcz[TY];      // H_old(k), kept for the H update
     float ecx[TY + 1], ecy[TY], ecz[TY + 1];  // E_new(k)
     float hxh[TY], eyh[TY], ezh[TY];          // lane 63: H_x(k), E_new(k) at x0+64
     float hyl[TY + 1], hzl[TY];               // lane 0: H at x0-1
 
-    // H of the own lane 63 to the exchange (for the right neighbour's lane 0)
-    auto put_h = [&](int buf, const float (&hy)[TY + 1], const float (&hz)[TY + 2]) {
-        if (right) {
-#pragma unroll
-            for (int r = 0; r <= TY; ++r) X.hy[buf][w][r] = hy[r];
-#pragma unroll
-            for (int r = 0; r < TY; ++r) X.hz[buf][w][r] = hz[r + 1];
-        }
-    };
-    // H at x0-1 for lane 0: memory for the first wave, exchange otherwise
-    auto get_left = [&](int buf, int kk) {
-        if (lane == 0) {
-            if (left_global) {
-#pragma unroll
-                for (int r = 0; r <= TY; ++r) {
-                    hyl[r] = T.ld_left(HY, kk, r);
-                    if (r < TY) hzl[r] = T.ld_left(HZ, kk, r);
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r <= TY; ++r) {
-                    hyl[r] = X.hy[buf][w - 1][r];
-                    if (r < TY) hzl[r] = X.hz[buf][w - 1][r];
-                }
-            }
-        }
-    };
-    auto put_e = [&](int buf, const float (&ey)[TY], const float (&ez)[TY + 1]) {
+    auto get_left = [&](int kk) {             // H at x0-1 for lane 0
         if (lane == 0) {
 #pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                X.ey[buf][w][r] = ey[r];
-                X.ez[buf][w][r] = ez[r];
+            for (int r = 0; r <= TY; ++r) {
+                hyl[r] = T.ld_left(HY, kk, r);
+                if (r < TY) hzl[r] = T.ld_left(HZ, kk, r);
             }
         }
     };
@@ -272,76 +235,61 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
     {
         const int km = kb == 0 ? nz - 1 : kb - 1;
         float hx[TY + 2], hy[TY + 1], hz[TY + 2], hxm[TY], hym[TY + 1];
-        if (active) {
 #pragma unroll
-            for (int r = -1; r <= TY; ++r) {
-                hx[r + 1] = T.ld(HX, kb, r);
-                hz[r + 1] = T.ld(HZ, kb, r);
-                if (r >= 0) {
-                    hy[r] = T.ld(HY, kb, r);
-                    hym[r] = T.ld(HY, km, r);
-                    ecx[r] = T.ld(EX, kb, r);
-                    ecz[r] = T.ld(EZ, kb, r);
-                }
-                if (r >= 0 && r < TY) {
-                    hxm[r] = T.ld(HX, km, r);
-                    ecy[r] = T.ld(EY, kb, r);
-                }
+        for (int r = -1; r <= TY; ++r) {
+            hx[r + 1] = T.ld(HX, kb, r);
+            hz[r + 1] = T.ld(HZ, kb, r);
+            if (r >= 0) {
+                hy[r] = T.ld(HY, kb, r);
+                hym[r] = T.ld(HY, km, r);
+                ecx[r] = T.ld(EX, kb, r);
+                ecz[r] = T.ld(EZ, kb, r);
             }
-            put_h(0, hy, hz);
+            if (r >= 0 && r < TY) {
+                hxm[r] = T.ld(HX, km, r);
+                ecy[r] = T.ld(EY, kb, r);
+            }
         }
-        __syncthreads();
-        if (active) {
-            get_left(0, kb);
-            e_plane<TY>(p, lane, n, kb, slot, hx, hy, hz, hxm, hym, hyl, hzl, ecx, ecy, ecz);
-            put_e(0, ecy, ecz);
-            if (right && right_global) {
+        get_left(kb);
+        e_plane<TY>(p, lane, n, kb, slot, hx, hy, hz, hxm, hym, hyl, hzl, ecx, ecy, ecz);
+        if (right) {
 #pragma unroll
-                for (int r = 0; r < TY; ++r) hxh[r] = T.ld_right(HX, km, r);
-                e_halo_right<TY>(p, T, n, kb, slot_h, hy, hz, hxh, eyh, ezh);
-            }
-#pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                hcx[r] = hx[r + 1];
-                hcy[r] = hy[r];
-                hcz[r] = hz[r + 1];
-            }
-            hcy[TY] = hy[TY];
-            store_e(kb, ecx, ecy, ecz);
+            for (int r = 0; r < TY; ++r) hxh[r] = T.ld_right(HX, km, r);
+            e_halo_right<TY>(p, T, n, kb, slot_h, hy, hz, hxh, eyh, ezh);
         }
+#pragma unroll
+        for (int r = 0; r < TY; ++r) {
+            hcx[r] = hx[r + 1];
+            hcy[r] = hy[r];
+            hcz[r] = hz[r + 1];
+        }
+        hcy[TY] = hy[TY];
+        store_e(kb, ecx, ecy, ecz);
     }
     const float2 th = p.colmap ? p.tH[n] : make_float2(0.f, 0.f);
 
-    int it = 0;
-    for (int k = kb; k < ke; ++k, ++it) {
+    for (int k = kb; k < ke; ++k) {
         const int kn = k + 1 == nz ? 0 : k + 1;
-        const int bn = (it + 1) & 1, bk = it & 1;
         float hx[TY + 2], hy[TY + 1], hz[TY + 2];
         float enx[TY + 1], eny[TY], enz[TY + 1];
-        if (active) {
 #pragma unroll
-            for (int r = -1; r <= TY; ++r) {
-                hx[r + 1] = T.ld(HX, kn, r);
-                hz[r + 1] = T.ld(HZ, kn, r);
-                if (r >= 0) {
-                    hy[r] = T.ld(HY, kn, r);
-                    enx[r] = T.ld(EX, kn, r);
-                    enz[r] = T.ld(EZ, kn, r);
-                }
-                if (r >= 0 && r < TY) eny[r] = T.ld(EY, kn, r);
+        for (int r = -1; r <= TY; ++r) {
+            hx[r + 1] = T.ld(HX, kn, r);
+            hz[r + 1] = T.ld(HZ, kn, r);
+            if (r >= 0) {
+                hy[r] = T.ld(HY, kn, r);
+                enx[r] = T.ld(EX, kn, r);
+                enz[r] = T.ld(EZ, kn, r);
             }
-            put_h(bn, hy, hz);
+            if (r >= 0 && r < TY) eny[r] = T.ld(EY, kn, r);
         }
-        __syncthreads();
-        if (!active) continue;
         // ---- E_new(k+1) -------------------------------------------------
-        get_left(bn, kn);
+        get_left(kn);
         e_plane<TY>(p, lane, n, kn, slot, hx, hy, hz, hcx, hcy, hyl, hzl, enx, eny, enz);
-        put_e(bn, eny, enz);
         float eyh_n[TY], ezh_n[TY];
-        if (right && right_global) e_halo_right<TY>(p, T, n, kn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
+        if (right) e_halo_right<TY>(p, T, n, kn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
 
-        // ---- H_new(k): E_new(k) at x0+64 from the exchange or the halo --
+        // ---- H_new(k) ---------------------------------------------------
         float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
         if (p.colmap) {
             qt0 = cmul(p.zph[2 * k], th);
@@ -352,13 +300,8 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
             float ey_ip = __shfl_down(ecy[r], 1, 64);
             float ez_ip = __shfl_down(ecz[r], 1, 64);
             if (right) {
-                if (right_global) {
-                    ey_ip = eyh[r];
-                    ez_ip = ezh[r];
-                } else {
-                    ey_ip = X.ey[bk][w + 1][r];
-                    ez_ip = X.ez[bk][w + 1][r];
-                }
+                ey_ip = eyh[r];
+                ez_ip = ezh[r];
             }
             // H_x -= S_y Δ_y E_z - S_z Δ_z E_y
             float vx = hcx[r] - (p.sy * (ecz[r + 1] - ecz[r]) - p.sz * (eny[r] - ecy[r]));
@@ -392,7 +335,7 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
             ecx[r] = enx[r];
             ecz[r] = enz[r];
         }
-        if (right && right_global) {
+        if (right) {
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
                 eyh[r] = eyh_n[r];
@@ -425,7 +368,7 @@ Interior interior(const Problem& p, int rows, int zchunk) {
 }
 
 int group_count(const Interior& I) {
-    return ((I.nseg + WAVES - 1) / WAVES) * I.nrow * I.ncz;
+    return I.nseg * ((I.nrow + WAVES - 1) / WAVES) * I.ncz;
 }
 
 template <int TY>
