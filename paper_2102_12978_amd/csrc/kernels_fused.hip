@@ -10,8 +10,10 @@
 // store covers whole lines) × TY y rows and marches along z over a chunk of
 // planes, keeping two planes of each field in registers.
 //   * x: lane l holds x = x0 + l; x neighbours move between lanes with
-//     cross-lane shuffles. Lane 0 loads H at x0-1 with single-lane loads;
-//     lane 63 forms E_new at x0+64 from single-lane loads of that column.
+//     cross-lane shuffles. The halo columns x0-1 (H for lane 0) and x0+64
+//     (from which E_new at x0+64 is formed for lane 63) are fetched per plane
+//     by one gather instruction, one value per lane, and broadcast to the
+//     wavefront with readlane; the x0+64 update is done wavefront-uniform.
 //     Wavefronts never wait for each other: there is no barrier, so each
 //     keeps its own loads in flight.
 //   * y: each lane holds rows j0-1 .. j0+TY of H and j0 .. j0+TY of E in
@@ -77,13 +79,6 @@ struct Tile {
     __device__ float ld(int c, int kk, int r) const {
         return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1]);
     }
-    // column x0 - 1 (used by lane 0) and column x0 + 64 (used by lane 63)
-    __device__ float ld_left(int c, int kk, int r) const {
-        return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1] - 4u * (unsigned)(lane + 1));
-    }
-    __device__ float ld_right(int c, int kk, int r) const {
-        return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1] + 4u * (unsigned)(SEG - lane));
-    }
     __device__ void st(int c, int kk, int r, float v) const {
         sto(fw[c], (unsigned)kk * pstride + ro[r + 1], v);
     }
@@ -128,31 +123,67 @@ __device__ __forceinline__ void e_plane(const Problem& p, int lane, long long n,
     }
 }
 
-// Lane 63: E_new(E_y, E_z) of rows 0..TY-1 at x0+64 on plane kk (the same
-// update as e_plane, with H at x0+63 from the lane's own registers).
-// hxh_km: H_x(x0+64) of plane kk-1, replaced by that of plane kk.
+// Halo columns. Lane 0 needs H_y (rows 0..TY) and H_z (rows 0..TY-1) at
+// x0-1; lane 63 needs E_new(E_y, E_z) at x0+64 (rows 0..TY-1), formed from
+// H_x (rows -1..TY-1), H_y, H_z, E_y, E_z (rows 0..TY-1) of that column.
+// Those 7 TY + 2 values of one plane are fetched by a single gather: lane q
+// loads value q, and the wavefront broadcasts them with readlane.
 template <int TY>
-__device__ __forceinline__ void e_halo_right(const Problem& p, const Tile<TY>& T, long long n,
-                                             int kk, const int (&slot_h)[TY],
+struct Halo {
+    static constexpr int R_HX = 0;              // x0+64: H_x rows -1..TY-1
+    static constexpr int R_HY = TY + 1;         //        H_y rows 0..TY-1
+    static constexpr int R_HZ = 2 * TY + 1;     //        H_z
+    static constexpr int R_EY = 3 * TY + 1;     //        E_y
+    static constexpr int R_EZ = 4 * TY + 1;     //        E_z
+    static constexpr int L_HY = 5 * TY + 1;     // x0-1:  H_y rows 0..TY
+    static constexpr int L_HZ = 6 * TY + 2;     //        H_z rows 0..TY-1
+    static constexpr int COUNT = 7 * TY + 2;
+    static_assert(COUNT <= 64, "halo gather exceeds one wavefront");
+};
+
+__device__ __forceinline__ float bcast(float v, int q) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), q));
+}
+
+// Element offset (from the old-parity field base, plane 0) of halo value q.
+template <int TY>
+__device__ __forceinline__ size_t halo_offset(const Problem& p, int q, int j0, int x0) {
+    using Hq = Halo<TY>;
+    int c = HX, r = -1, x = x0 + SEG;
+    if (q >= Hq::L_HZ) { c = HZ; r = q - Hq::L_HZ; x = x0 - 1; }
+    else if (q >= Hq::L_HY) { c = HY; r = q - Hq::L_HY; x = x0 - 1; }
+    else if (q >= Hq::R_EZ) { c = EZ; r = q - Hq::R_EZ; }
+    else if (q >= Hq::R_EY) { c = EY; r = q - Hq::R_EY; }
+    else if (q >= Hq::R_HZ) { c = HZ; r = q - Hq::R_HZ; }
+    else if (q >= Hq::R_HY) { c = HY; r = q - Hq::R_HY; }
+    else { r = q - 1; }
+    return (size_t)c * p.fstride + (size_t)(j0 + r) * p.pitch + x;
+}
+
+// E_new(E_y, E_z) at x0+64, rows 0..TY-1, of plane kk from the gathered
+// column g (uniform) and H at x0+63 (lane 63's registers; other lanes form
+// values nobody reads). hxkm: H_x(x0+64) of plane kk-1, replaced by plane kk.
+template <int TY>
+__device__ __forceinline__ void e_halo_right(const Problem& p, long long n, int kk, float g,
+                                             const int (&slot_h)[TY],
                                              const float (&hy)[TY + 1], const float (&hz)[TY + 2],
-                                             float (&hxh_km)[TY], float (&ey_h)[TY],
+                                             float (&hxkm)[TY], float (&ey_h)[TY],
                                              float (&ez_h)[TY]) {
+    using Hq = Halo<TY>;
     float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
     if (p.colmap) {
         const float2 t = p.tE[n];
         pt0 = cmul(p.zph[2 * kk], t);
         pt1 = cmul(p.zph[2 * kk + 1], t);
     }
-    float hx_prev = T.ld_right(HX, kk, -1);
+    float hx_prev = bcast(g, Hq::R_HX);
 #pragma unroll
     for (int r = 0; r < TY; ++r) {
-        const float hxr = T.ld_right(HX, kk, r);
-        const float hyr = T.ld_right(HY, kk, r);
-        const float hzr = T.ld_right(HZ, kk, r);
-        float vy = T.ld_right(EY, kk, r);
-        float vz = T.ld_right(EZ, kk, r);
-        vy += p.sz * (hxr - hxh_km[r]) - p.sx * (hzr - hz[r + 1]);
-        vz += p.sx * (hyr - hy[r]) - p.sy * (hxr - hx_prev);
+        const float hxr = bcast(g, Hq::R_HX + 1 + r);
+        float vy = bcast(g, Hq::R_EY + r) + p.sz * (hxr - hxkm[r]) -
+                   p.sx * (bcast(g, Hq::R_HZ + r) - hz[r + 1]);
+        float vz = bcast(g, Hq::R_EZ + r) + p.sx * (bcast(g, Hq::R_HY + r) - hy[r]) -
+                   p.sy * (hxr - hx_prev);
         if (slot_h[r] >= 0) {
             const float2* a = p.amp + (size_t)slot_h[r] * 6;
             vy += cmul_re(a[EY], pt0);
@@ -160,7 +191,7 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, const Tile<TY>& T
         }
         ey_h[r] = vy;
         ez_h[r] = vz;
-        hxh_km[r] = hxr;
+        hxkm[r] = hxr;
         hx_prev = hxr;
     }
 }
@@ -190,25 +221,29 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
     const int nz = p.nz, nx = p.nx, ny = p.ny;
     const bool right = lane == 63;
 
+    const int x0 = I.x_org + SEG * seg;
     int slot[TY + 1], slot_h[TY];
 #pragma unroll
     for (int r = 0; r <= TY; ++r) slot[r] = p.colmap ? p.colmap[(size_t)(j0 + r) * nx + T.x] : -1;
 #pragma unroll
     for (int r = 0; r < TY; ++r)
-        slot_h[r] = (p.colmap && right) ? p.colmap[(size_t)(j0 + r) * nx + T.x + 1] : -1;
+        slot_h[r] = p.colmap ? p.colmap[(size_t)(j0 + r) * nx + x0 + SEG] : -1;
+    // halo gather: lane q < Halo::COUNT fetches halo value q of each plane
+    const float* gbase = p.fbase[par] +
+                         halo_offset<TY>(p, lane < Halo<TY>::COUNT ? lane : 0, j0, x0);
+    const size_t plane_elems = (size_t)ny * p.pitch;
+    auto gather = [&](int kk) { return gbase[(size_t)kk * plane_elems]; };
 
     float hcx[TY], hcy[TY + 1], hcz[TY];      // H_old(k), kept for the H update
     float ecx[TY + 1], ecy[TY], ecz[TY + 1];  // E_new(k)
-    float hxh[TY], eyh[TY], ezh[TY];          // lane 63: H_x(k), E_new(k) at x0+64
-    float hyl[TY + 1], hzl[TY];               // lane 0: H at x0-1
+    float hxh[TY], eyh[TY], ezh[TY];          // H_x(k), E_new(k) at x0+64 (uniform)
+    float hyl[TY + 1], hzl[TY];               // H at x0-1 (uniform)
 
-    auto get_left = [&](int kk) {             // H at x0-1 for lane 0
-        if (lane == 0) {
+    auto get_left = [&](float g) {
 #pragma unroll
-            for (int r = 0; r <= TY; ++r) {
-                hyl[r] = T.ld_left(HY, kk, r);
-                if (r < TY) hzl[r] = T.ld_left(HZ, kk, r);
-            }
+        for (int r = 0; r <= TY; ++r) {
+            hyl[r] = bcast(g, Halo<TY>::L_HY + r);
+            if (r < TY) hzl[r] = bcast(g, Halo<TY>::L_HZ + r);
         }
     };
 
@@ -250,13 +285,12 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
                 ecy[r] = T.ld(EY, kb, r);
             }
         }
-        get_left(kb);
+        const float gm = gather(km), g0 = gather(kb);
+        get_left(g0);
         e_plane<TY>(p, lane, n, kb, slot, hx, hy, hz, hxm, hym, hyl, hzl, ecx, ecy, ecz);
-        if (right) {
 #pragma unroll
-            for (int r = 0; r < TY; ++r) hxh[r] = T.ld_right(HX, km, r);
-            e_halo_right<TY>(p, T, n, kb, slot_h, hy, hz, hxh, eyh, ezh);
-        }
+        for (int r = 0; r < TY; ++r) hxh[r] = bcast(gm, Halo<TY>::R_HX + 1 + r);
+        e_halo_right<TY>(p, n, kb, g0, slot_h, hy, hz, hxh, eyh, ezh);
 #pragma unroll
         for (int r = 0; r < TY; ++r) {
             hcx[r] = hx[r + 1];
@@ -283,11 +317,12 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
             }
             if (r >= 0 && r < TY) eny[r] = T.ld(EY, kn, r);
         }
+        const float gn = gather(kn);
         // ---- E_new(k+1) -------------------------------------------------
-        get_left(kn);
+        get_left(gn);
         e_plane<TY>(p, lane, n, kn, slot, hx, hy, hz, hcx, hcy, hyl, hzl, enx, eny, enz);
         float eyh_n[TY], ezh_n[TY];
-        if (right) e_halo_right<TY>(p, T, n, kn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
+        e_halo_right<TY>(p, n, kn, gn, slot_h, hy, hz, hxh, eyh_n, ezh_n);
 
         // ---- H_new(k) ---------------------------------------------------
         float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
@@ -335,12 +370,10 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
             ecx[r] = enx[r];
             ecz[r] = enz[r];
         }
-        if (right) {
 #pragma unroll
-            for (int r = 0; r < TY; ++r) {
-                eyh[r] = eyh_n[r];
-                ezh[r] = ezh_n[r];
-            }
+        for (int r = 0; r < TY; ++r) {
+            eyh[r] = eyh_n[r];
+            ezh[r] = ezh_n[r];
         }
     }
     if (epart_slot) {
