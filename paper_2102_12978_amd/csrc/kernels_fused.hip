@@ -198,7 +198,7 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, long long n, int 
 
 template <int TY>
 __global__ void __launch_bounds__(64 * WAVES)
-__attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 1)))
+__attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 2)))
 fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_padded,
                       double* epart) {
     // ---- which tile: hardware block b runs on XCD b % 8 ----------------
