@@ -66,13 +66,14 @@ void* balloc(fdtd_batch* b, size_t bytes) {
     return p;
 }
 
-// Work items: per instance, blocks of `cols` flattened (x, y) columns times
-// z ranges of `zchunk` planes (0: the whole z extent).
+// Work items: per instance, blocks of `cols` flattened (x, y) columns (x
+// running over the padded pitch) times z ranges of `zchunk` planes (0: the
+// whole z extent).
 void build_work(fdtd_batch* b) {
     std::vector<int4> w;
     for (int q = 0; q < (int)b->inst.size(); ++q) {
         const Problem& p = b->inst[q]->p;
-        const int ncol = p.nx * p.ny;
+        const int ncol = p.pitch * p.ny;   // columns over the padded pitch (x >= nx idle)
         const int zc = b->zchunk > 0 ? std::min(b->zchunk, p.nz) : p.nz;
         for (int c0 = 0; c0 < ncol; c0 += b->cols)
             for (int k0 = 0; k0 < p.nz; k0 += zc) w.push_back(make_int4(q, c0, k0, std::min(k0 + zc, p.nz)));

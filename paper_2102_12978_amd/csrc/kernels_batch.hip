@@ -1,8 +1,9 @@
 // Batched Yee step over many independent instances of uneven size. All
 // instances advance in lockstep: one E launch and one H launch per step walk
 // a single flattened list of work items (instance, block of flattened (x, y)
-// columns, z range) with a persistent grid, so small instances do not leave
-// the chip idle and the whole step is two launches regardless of the
+// columns over the padded row pitch, so that a wavefront reads one aligned
+// 256-byte row segment, z range) with a persistent grid, so small instances
+// do not leave the chip idle and the whole step is two launches regardless of the
 // instance count. The per-cell arithmetic is the split kernels' (every
 // boundary case, the antenna source and the plane accumulation), so an
 // instance advances bit-identically to a single-domain split-kernel run.
@@ -31,8 +32,8 @@ batch_e_kernel(const Problem* __restrict__ probs, const int4* __restrict__ work,
         const int4 wk = work[w];
         const Problem p = probs[wk.x];   // a copy: stores below cannot alias it
         const int col = wk.y + (int)threadIdx.x;
-        if (col >= p.nx * p.ny) continue;
-        const int i = col % p.nx, j = col / p.nx;
+        const int i = col % p.pitch, j = col / p.pitch;
+        if (i >= p.nx || j >= p.ny) continue;
         const int mask = (diag && n >= p.win_begin) ? p.diag_mask : 0;
         for (int k = wk.z; k < wk.w; ++k) (void)e_point(p, n, par, i, j, k, mask);
     }
@@ -47,8 +48,8 @@ batch_h_kernel(const Problem* __restrict__ probs, const int4* __restrict__ work,
         const int4 wk = work[w];
         const Problem p = probs[wk.x];
         const int col = wk.y + (int)threadIdx.x;
-        if (col >= p.nx * p.ny) continue;
-        const int i = col % p.nx, j = col / p.nx;
+        const int i = col % p.pitch, j = col / p.pitch;
+        if (i >= p.nx || j >= p.ny) continue;
         for (int k = wk.z; k < wk.w; ++k) (void)h_point(p, n, par, i, j, k);
     }
 }

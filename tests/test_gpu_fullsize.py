@@ -1,0 +1,67 @@
+"""Parity at the benchmark's full size: 768×768×255, Δx = λ/24, θ = 20°,
+order 2, annulus 320Δx, 16-cell CPML, in the benchmark's launch shape (fused
+interior kernel, 4 rows per wavefront, z chunks of 16, split frame).
+
+From a seeded random state (fields U(-1,1), random CPML memories, E held at
+the walls zeroed) and with the antenna on, three steps run on the GPU; then
+whole z-columns at sampled (x, y) positions are compared with the FP64
+oracle, each computed exactly from a small window of the same initial state
+(tests/window.py). The columns sit on interior segment and row-group
+boundaries (x0 - 1 / x0, last / first row of a group), on the interior's
+edge and the frame next to it, in the CPML slabs and corners, and on the
+antenna ring; every z plane of each column is compared, so every z-chunk
+boundary is crossed."""
+import numpy as np
+import pytest
+
+from oracle import problem as P
+from oracle import yee as Y
+from paper_2102_12978_amd import _lib as L
+from paper_2102_12978_amd import workloads as W
+from tests import cases
+from tests import gpu_cases as GC
+from tests import window as WN
+
+pytestmark = pytest.mark.gpu
+
+COLUMNS = [(95, 100), (96, 101), (32, 17), (31, 16), (735, 748), (736, 749), (400, 20),
+           (400, 21), (8, 400), (760, 400), (400, 760), (5, 5), (762, 762), (704, 384),
+           (384, 64), (610, 610), (159, 383), (160, 384)]
+
+
+def test_large_grid_sampled_columns():
+    w = W.config2()
+    steps = 3
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=16)
+    g = cases.oracle_grid(w)
+    ant = P.build_antenna(g, cases.oracle_injector(w))
+    rng = np.random.default_rng(7)
+    fields = {}
+    for q, c in enumerate(GC.COMPS):
+        a = rng.uniform(-1.0, 1.0, size=(g.nz, g.ny, g.nx)).astype(np.float32)
+        if c in ("ex", "ey", "ez"):
+            a[:, Y.held_mask(g, c)] = 0.0
+        s.set_state(q, a)
+        fields[c] = a
+    slabs = {}
+    for q, name in GC.PSI.items():
+        a = rng.uniform(-1.0, 1.0, size=s.state_shape(q)).astype(np.float32)
+        s.set_state(q, a)
+        slabs[name] = a
+    print(f"  random state set; {steps} steps in the benchmark launch shape", flush=True)
+    s.step(steps)
+    got = {c: s.get_state(q) for q, c in enumerate(GC.COMPS)}
+    s.close()
+    num = den = 0.0
+    worst = 0.0
+    for (i, j) in COLUMNS:
+        ref = WN.column(g, ant, fields, slabs, i, j, steps)
+        for c in GC.COMPS:
+            d = got[c][:, j, i].astype(np.float64) - ref[c]
+            num += float(np.sum(d * d))
+            den += float(np.sum(ref[c] ** 2))
+            worst = max(worst, float(np.abs(d).max()))
+    rel = (num / den) ** 0.5
+    print(f"  {len(COLUMNS)} columns x {g.nz} planes x 6 components: rel-L2 {rel:.2e}, "
+          f"max |diff| {worst:.2e}", flush=True)
+    assert rel <= 1e-5 and worst <= 1e-5
