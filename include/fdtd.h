@@ -310,10 +310,11 @@ int fdtd_adjoint_get_info(const fdtd_adjoint *a, fdtd_adjoint_info *out);
  * A batch owns `count` solver contexts of uneven grid size, cone angle and
  * order (each made as by fdtd_create with FDTD_KERNEL_SPLIT on the batch's
  * stream, then fdtd_set_injector) and advances them in lockstep. Every step
- * is one E launch and one H launch that walk a single flattened list of work
- * items (instance, block of `cols` flattened (x, y) columns, z range of
- * `zchunk` planes) with a persistent grid; the per-cell arithmetic is that
- * of the split kernels, so every instance evolves bit-identically to a
+ * walks a single flattened list of work items covering all instances with a
+ * persistent grid: by default an E launch and an H launch over blocks of
+ * flattened columns, or one fused launch over tiles (instance, 64 x cells,
+ * 4 rows, z chunk). Either way the per-cell arithmetic is that of the
+ * split kernels, so every instance evolves bit-identically to a
  * single-domain FDTD_KERNEL_SPLIT run of the same problem. Runs of
  * graph_steps steps are recorded once into a HIP graph and replayed; the
  * step index lives in a device counter so a replay stays valid. */
@@ -329,6 +330,8 @@ typedef struct fdtd_batch_info {
     int64_t cells;               /* sum of nx*ny*nz over the instances         */
     int64_t step;                /* completed steps                            */
     int64_t device_bytes;        /* device memory held by batch and instances  */
+    int32_t kernel;              /* FDTD_KERNEL_FUSED or FDTD_KERNEL_SPLIT      */
+    int32_t reserved;
 } fdtd_batch_info;
 
 /* Create a batch. grids[count] (their stream and kernel fields are ignored:
@@ -359,17 +362,26 @@ fdtd_ctx *fdtd_batch_instance(fdtd_batch *b, int32_t q);
 /* Advance every instance nsteps steps (asynchronous on the batch's stream). */
 int fdtd_batch_step(fdtd_batch *b, int64_t nsteps);
 
-/* Work-item shape: cols in {64, 128, 256}, zchunk >= 0 (0 = whole z). */
+/* Step kernel: FDTD_KERNEL_SPLIT (default: an E launch and an H launch
+ * over flattened columns) or FDTD_KERNEL_FUSED (one launch per step over
+ * tiles of 64 x cells by 4 rows marching through a z chunk, the boundary
+ * cases handled per cell; bit-identical to the split kernels). The
+ * autotuner tries both. */
+int fdtd_batch_set_kernel(fdtd_batch *b, int32_t kernel);
+
+/* Work-item shape: cols in {64, 128, 256} (split kernel only), zchunk >= 0
+ * (z planes per work item, 0 = whole z). */
 int fdtd_batch_set_tile(fdtd_batch *b, int32_t cols, int32_t zchunk);
 
 /* Steps recorded per graph: an even number in [2, 1000], or 0 to launch
  * every step directly. */
 int fdtd_batch_set_graph_steps(fdtd_batch *b, int32_t steps);
 
-/* Time every work-item shape (cols x zchunk in {64, 128, 256} x
- * {0, 16, 8, 4, 1})
- * for steps_per_trial steps on the live state, keep the fastest. Trials
- * write only the buffers of the next parity, so the state is unchanged. */
+/* Time every kernel and work-item shape (fused with zchunk in
+ * {0, 32, 16, 8}; split with cols x zchunk in {64, 128, 256} x
+ * {0, 16, 8, 4, 1}) for steps_per_trial steps on the live state and keep
+ * the fastest; *best_cols is 0 when the fused kernel wins. Trials write only
+ * the buffers of the next parity, so the state is unchanged. */
 int fdtd_batch_autotune(fdtd_batch *b, int32_t steps_per_trial, int32_t *best_cols,
                         int32_t *best_zchunk);
 

@@ -60,7 +60,8 @@ class BatchInfo(ctypes.Structure):
                 ("tile_zchunk", ctypes.c_int32), ("work_items", ctypes.c_int32),
                 ("blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
                 ("cells", ctypes.c_int64), ("step", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("kernel", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class AdjointInfo(ctypes.Structure):
@@ -122,6 +123,7 @@ _SIGS = {
     "fdtd_batch_step": (ctypes.c_int, [_BATCH, ctypes.c_int64]),
     "fdtd_batch_set_tile": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_batch_set_graph_steps": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
+    "fdtd_batch_set_kernel": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
     "fdtd_batch_autotune": (ctypes.c_int, [_BATCH, ctypes.c_int32, _I32P, _I32P]),
     "fdtd_batch_get_info": (ctypes.c_int, [_BATCH, ctypes.POINTER(BatchInfo)]),
 }

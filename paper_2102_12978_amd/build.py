@@ -16,7 +16,8 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function"]
 SOURCES = ["host_setup.cpp", "capi.cpp", "batch.cpp", "adjoint.cpp", "kernels_split.hip",
-           "kernels_fused.hip", "kernels_batch.hip", "kernels_adjoint.hip"]
+           "kernels_fused.hip", "kernels_fused_bnd.hip", "kernels_batch.hip",
+           "kernels_adjoint.hip"]
 
 
 def hipcc():

@@ -22,6 +22,7 @@ struct fdtd_batch {
     int4* work = nullptr;
     int nwork = 0;
     int cols = 256, zchunk = 0, blocks = 0;
+    int kernel = FDTD_KERNEL_SPLIT;    // split E/H passes, or fused boundary tiles
     int graph_steps = 20;              // even, so a replay leaves the parity unchanged
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // per starting parity
     int cu_count = 256;
@@ -66,13 +67,25 @@ void* balloc(fdtd_batch* b, size_t bytes) {
     return p;
 }
 
-// Work items: per instance, blocks of `cols` flattened (x, y) columns (x
-// running over the padded pitch) times z ranges of `zchunk` planes (0: the
-// whole z extent).
+// z chunk of the fused tiles (0: whole z, i.e. larger than any instance)
+int fused_cz(const fdtd_batch* b) { return b->zchunk > 0 ? b->zchunk : (1 << 30); }
+
+// Work items. Split kernels: per instance, blocks of `cols` flattened (x, y)
+// columns (x running over the padded pitch) times z ranges of `zchunk`
+// planes (0: the whole z extent). Fused kernel: per instance and z chunk,
+// tiles of 64 x cells by BND_ROWS rows, x fastest so that consecutive tiles
+// are x-adjacent.
 void build_work(fdtd_batch* b) {
     std::vector<int4> w;
     for (int q = 0; q < (int)b->inst.size(); ++q) {
         const Problem& p = b->inst[q]->p;
+        if (b->kernel == FDTD_KERNEL_FUSED) {
+            const int cz = std::min(fused_cz(b), p.nz);
+            for (int c = 0; c * cz < p.nz; ++c)
+                for (int y0 = 0; y0 < p.ny; y0 += BND_ROWS)
+                    for (int x0 = 0; x0 < p.nx; x0 += 64) w.push_back(make_int4(q, x0, y0, c));
+            continue;
+        }
         const int ncol = p.pitch * p.ny;   // columns over the padded pitch (x >= nx idle)
         const int zc = b->zchunk > 0 ? std::min(b->zchunk, p.nz) : p.nz;
         for (int c0 = 0; c0 < ncol; c0 += b->cols)
@@ -90,8 +103,13 @@ void build_work(fdtd_batch* b) {
     b->work = static_cast<int4*>(balloc(b, w.size() * sizeof(int4)));
     check(hipMemcpy(b->work, w.data(), w.size() * sizeof(int4), hipMemcpyHostToDevice), "copy work");
     // persistent grid: as many workgroups as can be resident at once
-    const int per_cu = batch_blocks_per_cu(b->cols);
-    b->blocks = std::max(1, std::min(b->nwork, b->cu_count * per_cu));
+    if (b->kernel == FDTD_KERNEL_FUSED) {
+        const int per_cu = fused_bnd_blocks_per_cu();
+        b->blocks = std::max(1, std::min((b->nwork + 3) / 4, b->cu_count * per_cu));
+    } else {
+        const int per_cu = batch_blocks_per_cu(b->cols);
+        b->blocks = std::max(1, std::min(b->nwork, b->cu_count * per_cu));
+    }
 }
 
 // Push every instance's Problem (with its diagnostics selection) to the
@@ -116,6 +134,9 @@ void upload_problems(fdtd_batch* b, bool force = false) {
 }
 
 hipError_t launch_pair(const fdtd_batch* b, hipStream_t s, int off, int par, int diag) {
+    if (b->kernel == FDTD_KERNEL_FUSED)
+        return launch_fused_bnd(b->host_probs[0], b->probs, b->work, b->nwork, fused_cz(b),
+                                b->blocks, b->nctr, off, par, diag, Frame{0, 0, 0, 0}, nullptr, s);
     hipError_t e = launch_batch_e(b->probs, b->work, b->nwork, b->cols, b->blocks, b->nctr, off,
                                   par, diag, s);
     if (e != hipSuccess) return e;
@@ -269,6 +290,16 @@ int fdtd_batch_set_tile(fdtd_batch* b, int32_t cols, int32_t zchunk) {
     });
 }
 
+int fdtd_batch_set_kernel(fdtd_batch* b, int32_t kernel) {
+    if (!b) return FDTD_EINVAL;
+    return bguard(b, [&] {
+        need(kernel == FDTD_KERNEL_FUSED || kernel == FDTD_KERNEL_SPLIT,
+             "kernel must be FDTD_KERNEL_FUSED or FDTD_KERNEL_SPLIT");
+        b->kernel = kernel;
+        build_work(b);
+    });
+}
+
 int fdtd_batch_set_graph_steps(fdtd_batch* b, int32_t steps) {
     if (!b) return FDTD_EINVAL;
     return bguard(b, [&] {
@@ -290,36 +321,42 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
         hipEvent_t e0, e1;
         check(hipEventCreate(&e0), "event");
         check(hipEventCreate(&e1), "event");
-        int bc = b->cols, bz = b->zchunk;
+        int bk = b->kernel, bc = b->cols, bz = b->zchunk;
         float best = -1.f;
+        struct Cand { int kernel, cols, zc; };
+        std::vector<Cand> cands;
+        for (int zc : {0, 32, 16, 8}) cands.push_back({FDTD_KERNEL_FUSED, b->cols, zc});
+        for (int cols : {64, 128, 256})
+            for (int zc : {0, 16, 8, 4, 1}) cands.push_back({FDTD_KERNEL_SPLIT, cols, zc});
         // Trials read the live parity and write the other one only, with the
         // plane accumulation off, so the state is left as it was.
-        for (int cols : {64, 128, 256}) {
-            for (int zc : {0, 16, 8, 4, 1}) {
-                b->cols = cols;
-                b->zchunk = zc;
-                build_work(b);
+        for (const Cand& cd : cands) {
+            b->kernel = cd.kernel;
+            b->cols = cd.cols;
+            b->zchunk = cd.zc;
+            build_work(b);
+            check(launch_pair(b, b->stream, 0, b->parity, 0), "trial");
+            check(hipEventRecord(e0, b->stream), "event");
+            for (int t = 0; t < steps_per_trial; ++t)
                 check(launch_pair(b, b->stream, 0, b->parity, 0), "trial");
-                check(hipEventRecord(e0, b->stream), "event");
-                for (int t = 0; t < steps_per_trial; ++t)
-                    check(launch_pair(b, b->stream, 0, b->parity, 0), "trial");
-                check(hipEventRecord(e1, b->stream), "event");
-                check(hipEventSynchronize(e1), "event sync");
-                float ms = 0.f;
-                check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-                if (best < 0.f || ms < best) {
-                    best = ms;
-                    bc = cols;
-                    bz = zc;
-                }
+            check(hipEventRecord(e1, b->stream), "event");
+            check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+            if (best < 0.f || ms < best) {
+                best = ms;
+                bk = cd.kernel;
+                bc = cd.cols;
+                bz = cd.zc;
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        b->kernel = bk;
         b->cols = bc;
         b->zchunk = bz;
         build_work(b);
-        if (best_cols) *best_cols = bc;
+        if (best_cols) *best_cols = bk == FDTD_KERNEL_FUSED ? 0 : bc;
         if (best_zchunk) *best_zchunk = bz;
     });
 }
@@ -340,6 +377,7 @@ int fdtd_batch_get_info(const fdtd_batch* b, fdtd_batch_info* out) {
     r.graph_steps = b->graph_steps;
     r.step = b->step;
     r.device_bytes = bytes;
+    r.kernel = b->kernel;
     *out = r;
     return FDTD_OK;
 }

@@ -30,10 +30,12 @@ def _same(a, b):
     return all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
-def test_batch_equals_single_split_runs():
+@pytest.mark.parametrize("kernel", [L.KERNEL_FUSED, L.KERNEL_SPLIT])
+def test_batch_equals_single_split_runs(kernel):
     ws = W.batch_small()
     print(f"[gpu case] batch of {len(ws)}: " + ", ".join(w.name for w in ws), flush=True)
     b = Batch(ws)
+    b.set_kernel(kernel)
     b.set_graph_steps(20)
     b.step(45)            # two graph replays, then five direct steps (odd: parity flips)
     for q, w in enumerate(ws):
@@ -78,8 +80,8 @@ def test_autotune_leaves_state_alone():
     a = Batch(ws)
     a.step(10)
     cols, zc = a.autotune(2)
-    print(f"  batch autotune picked cols={cols} zchunk={zc}", flush=True)
-    assert cols in (64, 128, 256) and zc in (0, 16, 8, 4, 1)
+    print(f"  batch autotune picked kernel={a.info().kernel} cols={cols} zchunk={zc}", flush=True)
+    assert cols in (0, 64, 128, 256) and zc in (0, 32, 16, 8, 4, 1)
     a.step(30)
     b = Batch(ws)
     b.step(40)
@@ -89,10 +91,12 @@ def test_autotune_leaves_state_alone():
     b.close()
 
 
-@pytest.mark.parametrize("cols,zchunk", [(64, 5), (128, 0)])
-def test_tile_shapes_agree(cols, zchunk):
+@pytest.mark.parametrize("kernel,cols,zchunk", [(L.KERNEL_SPLIT, 64, 5), (L.KERNEL_SPLIT, 128, 0),
+                                                (L.KERNEL_FUSED, 64, 5), (L.KERNEL_FUSED, 64, 0)])
+def test_tile_shapes_agree(kernel, cols, zchunk):
     ws = W.batch_small()
     a = Batch(ws)
+    a.set_kernel(kernel)
     a.set_tile(cols, zchunk)
     a.step(24)
     for q, w in enumerate(ws):
@@ -142,7 +146,8 @@ def test_config3_batch_sampled_instances():
     cols, zc = b.autotune(1)
     b.set_graph_steps(20)
     inf = b.info()
-    print(f"  c3: {inf.count} instances, {inf.cells / 1e6:.2f} M cells, cols={cols} zchunk={zc}, "
+    print(f"  c3: {inf.count} instances, {inf.cells / 1e6:.2f} M cells, kernel={inf.kernel} "
+          f"cols={cols} zchunk={zc}, "
           f"{inf.work_items} work items, {inf.blocks} workgroups", flush=True)
     assert inf.count == 64 and inf.cells == 48_492_676   # sum of nx ny nz after the z fits
     b.step(24)
