@@ -251,6 +251,13 @@ def main():
                 "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": info.interior_cells,
                 "bytes_per_launch": bytes_launch}
     step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
+    if roof:
+        # what a kernel with no arithmetic reaches on the same GPU (context for frac)
+        from paper_2102_12978_amd.hbm_copy import stream_ceiling
+        ceil = stream_ceiling(stream=stream.cuda_stream)
+        roof["stream_ceiling"] = ceil
+        roof["frac_of_copy"] = round(roof["achieved"] / ceil["copy_gbs"], 4)
+        log(f"[bench] streaming probe: {ceil}")
     out = {
         "metric": "Gcell-updates/s (Yee E+H+CPML+inject)",
         "value": round(value, 2),

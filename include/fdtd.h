@@ -240,6 +240,23 @@ int fdtd_profile_enable(fdtd_ctx *ctx, int32_t on);
 /* Copy up to max entries; *count receives the number of kernel names. */
 int fdtd_profile_read(fdtd_ctx *ctx, fdtd_kernel_profile *out, int32_t max, int32_t *count);
 
+/* ---- memory-roofline probe ------------------------------------------------
+ * Not part of the method: the measurement that the Yee kernels' HBM
+ * fraction is read against. Allocates two device buffers of `bytes` bytes
+ * each (freed before returning), then times `reps` passes of a plain
+ * streaming kernel on `stream` (NULL: the null stream) with HIP events:
+ *   FDTD_PROBE_COPY  reads one buffer and writes the other (2·bytes moved);
+ *   FDTD_PROBE_READ  reads one buffer (bytes moved);
+ *   FDTD_PROBE_WRITE writes one buffer (bytes moved).
+ * bytes must be a positive multiple of 16; reps in [1, 1000]. On success
+ * *ms_per_pass is the mean pass time and *gbs the moved bytes per second
+ * in GB/s. Synchronous; returns FDTD_ENOMEM if the buffers cannot be had. */
+#define FDTD_PROBE_COPY  0
+#define FDTD_PROBE_READ  1
+#define FDTD_PROBE_WRITE 2
+int fdtd_stream_probe(int32_t kind, int64_t bytes, int32_t reps, void *stream,
+                      double *ms_per_pass, double *gbs);
+
 /* ---- adjoint: gradient of an intensity loss w.r.t. the sector weights ----
  * The scheme is linear in (E, H̃, ψ) plus an additive source, so reverse-
  * mode differentiation is the transposed step run backwards in time: for a

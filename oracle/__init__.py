@@ -13,6 +13,7 @@ Modules
               time factors (paper §4)
 ``yee``       second-order Yee leapfrog with CPML, z-periodic boundary and the
               soft-source injection (paper §4), plus the diagnostics (§5)
+``pulse``     the Bessel pulse of §3.2 (Gaussian spectrum) by quadrature
 ``adjoint``   the exact transpose of one ``yee`` step (for the gradient path)
 ``torch_ref`` a pure-PyTorch FP64 forward used as an autograd reference
 

@@ -126,6 +126,8 @@ _SIGS = {
     "fdtd_batch_set_kernel": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
     "fdtd_batch_autotune": (ctypes.c_int, [_BATCH, ctypes.c_int32, _I32P, _I32P]),
     "fdtd_batch_get_info": (ctypes.c_int, [_BATCH, ctypes.POINTER(BatchInfo)]),
+    "fdtd_stream_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_void_p, c_double_p, c_double_p]),
 }
 
 _lib = None

@@ -76,10 +76,10 @@ class Solver:
                 kernel=kernel, stream=stream)
         return s
 
-    def set_workload_injector(self, w: W.Workload, sector_amp=None, sector_phase=None,
-                              ramp_kind=L.RAMP_SIN2):
+    def set_workload_injector(self, w: W.Workload, sector_amp=None, sector_phase=None):
+        kind, a, b = w.ramp_args
         self.set_injector(W.WAVELENGTH, w.theta, w.order, w.e0, w.r_outer_cells * w.dx,
-                          w.thickness_cells * w.dx, ramp_kind=ramp_kind, ramp_a=w.ramp_seconds,
+                          w.thickness_cells * w.dx, ramp_kind=kind, ramp_a=a, ramp_b=b,
                           sector_amp=sector_amp, sector_phase=sector_phase)
 
     # -- API --------------------------------------------------------------

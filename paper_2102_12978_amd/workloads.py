@@ -48,6 +48,9 @@ class Workload:
     sigma_scale: float = 1.0
     kappa_max: float = 1.0
     window_periods: float = 5.0
+    ramp_kind: int = RAMP_SIN2
+    pulse_t_fs: float = 0.0            # Gaussian envelope: T (fs)
+    pulse_t0_fs: float = 0.0           # Gaussian envelope: peak time T0 (fs)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -65,6 +68,14 @@ class Workload:
     @property
     def ramp_seconds(self):
         return self.ramp_periods * PERIOD
+
+    @property
+    def ramp_args(self):
+        """(kind, a, b) of the injector envelope in seconds: sin² turn-on
+        (a = T_r) or Gaussian (a = T, b = T0)."""
+        if self.ramp_kind == RAMP_GAUSS:
+            return RAMP_GAUSS, self.pulse_t_fs * 1e-15, self.pulse_t0_fs * 1e-15
+        return self.ramp_kind, self.ramp_seconds, 0.0
 
     @property
     def steps_per_period(self):
@@ -171,6 +182,52 @@ def validation_run(order=0, n_perp=2, ns=16.0):
     nz_hint = int(round(ns / math.cos(math.radians(th))))
     return Workload(f"v_theta30_m{order}_nperp{n_perp}_ns{int(ns)}", n, n, nz_hint, ns, th,
                     order, r_b, ns, npml, steps, ramp_periods=ramp_p)
+
+
+# The paper's parameter sets (§4 Table 1): order m, cone angle θ (deg),
+# antenna thickness δs (λ), N_parallel, N_perp.
+TABLE1 = {
+    "A": (0, 30.0, 1.0, 1, 4), "B": (1, 30.0, 1.0, 1, 4), "C": (2, 30.0, 1.0, 1, 4),
+    "D": (0, 25.0, 1.0, 1, 4), "E": (0, 17.0, 1.0, 1, 4), "F": (0, 25.0, 2.0, 1, 4),
+    "G": (0, 25.0, 3.0, 1, 4), "H": (0, 25.0, 1.0, 1, 3), "I": (0, 25.0, 1.0, 1, 2),
+}
+PULSE_T_FS, PULSE_T0_FS = 60.0, 180.0        # §5: T = 60 fs (100 fs FWHM), T0 = 180 fs
+RUN_ABC_COMPARE_FS = 213.5                    # §5: snapshot time of runs A-C
+
+
+def table1_run(name, ns=20, npml=6):
+    """Run `name` of Table 1 (§4): n_s = 20 cells per λ, cubic cells, 6-cell
+    CPML; transverse points int(2 n_s N_perp / sin θ) + 2 N_PML (the sampling
+    rule of §4), outer radius R_B = N_perp λ_xy at the CPML interface,
+    thickness δs; z periodic over 2 N_parallel axial periods (the z-fit
+    replaces the rule's int() and z CPML cells); Gaussian envelope T = 60 fs,
+    T0 = 180 fs (§5). The run lasts until the comparison time: 213.5 fs for
+    runs A-C (§5), otherwise the whole optical period nearest to the peak
+    time at the centre, T0 + R_B / (c sin θ)."""
+    m, th, ds, npar, nperp = TABLE1[name]
+    s = math.sin(math.radians(th))
+    lam_xy = ns / s                                   # cells
+    n = int(2 * ns * nperp / s) + 2 * npml
+    nz_hint = int(round(2 * npar * ns / math.cos(math.radians(th))))
+    if name in "ABC":
+        t_cmp = RUN_ABC_COMPARE_FS * 1e-15
+    else:
+        t_peak = PULSE_T0_FS * 1e-15 + nperp * lam_xy * (WAVELENGTH / ns) / (C_LIGHT * s)
+        t_cmp = round(t_peak / PERIOD) * PERIOD
+    steps = int(round(t_cmp / PERIOD * ns / 0.5))
+    return Workload(f"table1_{name}_m{m}_theta{th:g}_ds{ds:g}_nperp{nperp}", n, n, nz_hint,
+                    float(ns), th, m, nperp * lam_xy, ds * ns, npml, steps,
+                    ramp_kind=RAMP_GAUSS, pulse_t_fs=PULSE_T_FS, pulse_t0_fs=PULSE_T0_FS,
+                    extra={"run": name, "compare_s": t_cmp})
+
+
+def parity_gauss():
+    """Gaussian-envelope parity case: 120×96×(20 hint), Δx = λ/14, θ = 25°,
+    m = 1, R_B = 30Δx, δs = 4Δx, 10-cell CPML, T = 2 periods peaking at
+    T0 = 3 periods, 84 steps (three periods)."""
+    per_fs = PERIOD * 1e15
+    return Workload("p_gauss_120x96x20_theta25_m1", 120, 96, 20, 14.0, 25.0, 1, 30.0, 4.0, 10,
+                    84, ramp_kind=RAMP_GAUSS, pulse_t_fs=2 * per_fs, pulse_t0_fs=3 * per_fs)
 
 
 def random_fields(shape, seed=0):

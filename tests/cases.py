@@ -17,7 +17,8 @@ def oracle_grid(w: W.Workload, bc=None, nz=None, dz=None):
 
 
 def oracle_injector(w: W.Workload, amp=None, phase=None, e0=None):
+    kind, a, b = w.ramp_args
     return P.Injector(W.WAVELENGTH, w.theta, w.order, w.e0 if e0 is None else e0,
                       w.r_outer_cells * w.dx, w.thickness_cells * w.dx,
-                      ramp_kind=P.RAMP_SIN2, ramp_a=w.ramp_seconds,
+                      ramp_kind=kind, ramp_a=a, ramp_b=b,
                       sector_amp=amp, sector_phase=phase)

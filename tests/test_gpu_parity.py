@@ -50,6 +50,19 @@ def test_config0_forward(kernel):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", [L.KERNEL_SPLIT, L.KERNEL_FUSED])
+def test_gaussian_envelope(kernel):
+    """The paper's Gaussian envelope f(t) = exp(-(t - T0)²/T²) with the phase
+    referred to T0 (§4, zeroth-order approximation): 120×96, θ = 25°, m = 1,
+    T = 2 periods, T0 = 3 periods, 84 steps through the peak."""
+    w = W.parity_gauss()
+    s = GC.gpu_solver(w, kernel=kernel)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
 @pytest.mark.parametrize("rows,zchunk", [(4, 0), (8, 0), (4, 7), (8, 9)])
 def test_fused_interior_frame_and_fixup(rows, zchunk):
     """300×150: three fused segments, ragged frame, z chunks that do not
