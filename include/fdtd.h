@@ -52,6 +52,21 @@ extern "C" {
 #define FDTD_RAMP_GAUSS 1     /* f = exp(-(t - T0)² / T²), phase e^{-iω(t-T0)}*/
 #define FDTD_RAMP_CW    2     /* f = 1                                        */
 
+/* ---- polarisation of the injected beam (§3.1) ----------------------------
+ * Hertz potential Π along x, y or z, J_m(K r) e^{imφ} e^{iβz}, Q = ∇×Π,
+ * R = ∇×Q (the printed Cartesian forms of §3.1), paired as
+ *   TE (the E2/H2 solution): Ẽ = i (E0/k) Q, H̃ = (E0/k²) R;
+ *   TM (the E1/H1 solution): Ẽ = (E0/k²) R, H̃ = -i (E0/k) Q.
+ * Π_x TE is the linearly y-polarised beam of the paper's runs, Π_y TE the
+ * x-polarised one; Π_z gives for m = 0 the azimuthal (TE) and radial (TM)
+ * polarisations. */
+#define FDTD_POL_X_TE 0
+#define FDTD_POL_Y_TE 1
+#define FDTD_POL_Z_TE 2
+#define FDTD_POL_X_TM 3
+#define FDTD_POL_Y_TM 4
+#define FDTD_POL_Z_TM 5
+
 /* ---- kernel choice ------------------------------------------------------ */
 #define FDTD_KERNEL_AUTO  0   /* fused kernel, tile shape from the autotuner  */
 #define FDTD_KERNEL_SPLIT 1   /* two kernels per step (E, then H)            */
@@ -114,7 +129,7 @@ typedef struct fdtd_injector {
     double ramp_a;            /* SIN2: T_r (s); GAUSS: T (s)                   */
     double ramp_b;            /* GAUSS: T0 (s)                                 */
     int32_t n_sectors;        /* 0, or number of angular sectors of weights    */
-    int32_t reserved;         /* set to 0                                      */
+    int32_t polarization;     /* FDTD_POL_* (0: Π_x TE, the paper's runs)      */
     const double *sector_amp;   /* host [n_sectors] amplitudes a_s, or NULL    */
     const double *sector_phase; /* host [n_sectors] phases φ_s (rad), or NULL  */
 } fdtd_injector;
@@ -131,6 +146,8 @@ typedef struct fdtd_info {
     int64_t step;                /* completed steps                           */
     int64_t device_bytes;        /* device memory held by the context         */
     int64_t interior_cells;      /* cells per step updated by the fused kernel */
+    int32_t frame;               /* FDTD_FRAME_* used around the interior     */
+    int32_t xalign;              /* interior x origin multiple (32 or 64)     */
 } fdtd_info;
 
 /* Library version string (static storage). */
@@ -210,7 +227,8 @@ int fdtd_get_info(const fdtd_ctx *ctx, fdtd_info *out);
 
 /* Analytic reference on the diagnostic plane: ½ E0² cos²θ J_m²(K r) at the
  * E_y positions (the time average of E_y² of the CW beam, §3.1/§5), written
- * to host_out[ny*nx]. Requires an injector. */
+ * to host_out[ny*nx]. Requires an injector of polarisation FDTD_POL_X_TE
+ * (FDTD_ESTATE otherwise). */
 int fdtd_analytic_ey2(fdtd_ctx *ctx, float *host_out, int64_t n);
 
 /* Select the fused kernel's tile shape explicitly: y rows per wavefront in
@@ -219,8 +237,20 @@ int fdtd_analytic_ey2(fdtd_ctx *ctx, float *host_out, int64_t n);
  * otherwise. */
 int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
 
-/* Time candidate tile shapes on the live problem (the state is restored) and
- * keep the fastest. *best_rows / *best_zchunk may be NULL. */
+/* How the fused kernel's frame (the CPML slabs, walls and the cells the
+ * interior's tiles leave over) is stepped:
+ *   FDTD_FRAME_SPLIT: the split E and H kernels, one thread per cell;
+ *   FDTD_FRAME_FUSED: one launch of the fused step over the 64 x 4 tiles
+ *     that hold frame cells, each cell through the same per-cell boundary
+ *     code (bit-identical results), marching a z chunk like the interior.
+ * xalign (32 or 64) rounds the interior's x origin up to a multiple of that
+ * many cells; 64 makes the frame's x strips whole tiles. */
+#define FDTD_FRAME_SPLIT 0
+#define FDTD_FRAME_FUSED 1
+int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign);
+
+/* Time candidate tile shapes and frame choices on the live problem (the state
+ * is restored) and keep the fastest. *best_rows / *best_zchunk may be NULL. */
 int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,
                   int32_t *best_zchunk);
 

@@ -33,7 +33,8 @@ def _u(nu, kr, phi):
 
 
 def hertz_x(m, k, theta, x, y, z):
-    """Π_x potential value J_m(K r) e^{i m φ} e^{i β z} (§3.1, Π_x)."""
+    """Potential value J_m(K r) e^{i m φ} e^{i β z} (§3.1); the three potentials
+    Π_x, Π_y, Π_z carry it along x̂, ŷ or ẑ."""
     K = k * np.sin(theta)
     beta = k * np.cos(theta)
     r = np.hypot(x, y)
@@ -65,6 +66,69 @@ def qr_x(m, k, theta, x, y):
           1j * K * K / 4 * (um2 - up2),
           1j * beta * K / 2 * (um1 - up1))
     return q, rr
+
+
+def qr_y(m, k, theta, x, y):
+    """Q = ∇×Π and R = ∇×∇×Π for Π_y (§3.1, Π_y case), as printed; same
+    conventions as qr_x."""
+    K = k * np.sin(theta)
+    beta = k * np.cos(theta)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r = np.hypot(x, y)
+    phi = np.arctan2(y, x)
+    kr = K * r
+    um = _u(m, kr, phi)
+    up1, um1 = _u(m + 1, kr, phi), _u(m - 1, kr, phi)
+    up2, um2 = _u(m + 2, kr, phi), _u(m - 2, kr, phi)
+    q = (-1j * beta * um,
+         np.zeros_like(um),
+         -K / 2 * (up1 - um1))
+    rr = (1j * K * K / 4 * (um2 - up2),
+          (k * k + beta * beta) / 2 * um - K * K / 4 * (up2 + um2),
+          -beta * K / 2 * (up1 + um1))
+    return q, rr
+
+
+def qr_z(m, k, theta, x, y):
+    """Q = ∇×Π and R = ∇×∇×Π for Π_z (§3.1, Π_z case), as printed; same
+    conventions as qr_x."""
+    K = k * np.sin(theta)
+    beta = k * np.cos(theta)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    r = np.hypot(x, y)
+    phi = np.arctan2(y, x)
+    kr = K * r
+    um = _u(m, kr, phi)
+    up1, um1 = _u(m + 1, kr, phi), _u(m - 1, kr, phi)
+    q = (1j * K / 2 * (up1 + um1),
+         K / 2 * (up1 - um1),
+         np.zeros_like(um))
+    rr = (-1j * beta * K / 2 * (up1 - um1),
+          -beta * K / 2 * (up1 + um1),
+          K * K * um)
+    return q, rr
+
+
+QR = {0: qr_x, 1: qr_y, 2: qr_z}
+
+
+def amplitudes(axis, tm, m, k, theta, e0, x, y):
+    """Complex amplitudes (Ex, Ey, Ez, Hx, Hy, Hz) of the Π_axis beam.
+
+    TE pairing (E ∝ Q, the E2/H2 solution): Ẽ = i (E0/k) Q, H̃ = (E0/k²) R.
+    TM pairing (E ∝ R, the E1/H1 solution): Ẽ = (E0/k²) R, H̃ = -i (E0/k) Q.
+    Both follow from ∇×Q = R and ∇×R = k² Q with ∇×Ẽ = i k H̃ (e^{-iωt},
+    c = 1, H̃ = η0 H); the TE case is the reading stated in the header."""
+    q, rr = QR[axis](m, k, theta, x, y)
+    if tm:
+        e = tuple(e0 / (k * k) * rc for rc in rr)
+        h = tuple(-1j * e0 / k * qc for qc in q)
+    else:
+        e = tuple(1j * e0 / k * qc for qc in q)
+        h = tuple(e0 / (k * k) * rc for rc in rr)
+    return e + h
 
 
 def te_x_amplitudes(m, k, theta, e0, x, y):

@@ -181,6 +181,7 @@ class Injector:
     ramp_b: float = 0.0
     sector_amp: np.ndarray = None
     sector_phase: np.ndarray = None
+    polarization: int = 0          # potential axis (0 x, 1 y, 2 z) + 3 for the TM pairing
 
 
 @dataclass
@@ -214,7 +215,10 @@ def _held(comp, g: Grid, jj, ii):
 
 
 def build_antenna(g: Grid, inj: Injector) -> Antenna:
-    """Source point set and amplitudes (§4 antenna + §3.1 TE fields)."""
+    """Source point set and amplitudes (§4 antenna + §3.1 fields of the
+    chosen potential and pairing; Π_x TE is the paper's y-polarised beam)."""
+    assert inj.polarization in range(6)
+    axis, tm = inj.polarization % 3, inj.polarization // 3
     ns = inj.wavelength / g.dx                   # cells per wavelength
     k = 2.0 * math.pi / ns
     ant = Antenna(k=k, beta=k * math.cos(inj.theta), omega=k)
@@ -234,7 +238,7 @@ def build_antenna(g: Grid, inj: Injector) -> Antenna:
         keep = ~_held(comp, g, jj, ii)
         jj, ii = jj[keep], ii[keep]
         xs, ys = (ii + ox) - ax, (jj + oy) * g.ry - ay
-        amp = fields.te_x_amplitudes(inj.order, k, inj.theta, inj.e0, xs, ys)[ci]
+        amp = fields.amplitudes(axis, tm, inj.order, k, inj.theta, inj.e0, xs, ys)[ci]
         amp = np.asarray(amp, dtype=np.complex128).reshape(-1)
         ant.idx[comp] = (jj, ii)
         ant.base[comp] = amp

@@ -10,6 +10,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
 BC_CPML, BC_PEC, BC_PERIODIC = 0, 1, 2
 RAMP_SIN2, RAMP_GAUSS, RAMP_CW = 0, 1, 2
 KERNEL_AUTO, KERNEL_SPLIT, KERNEL_FUSED = 0, 1, 2
+FRAME_SPLIT, FRAME_FUSED = 0, 1
+POL_X_TE, POL_Y_TE, POL_Z_TE, POL_X_TM, POL_Y_TM, POL_Z_TM = range(6)
 EX, EY, EZ, HX, HY, HZ = range(6)
 PSI_EXY, PSI_EYX, PSI_EZX, PSI_EZY, PSI_HXY, PSI_HYX, PSI_HZX, PSI_HZY = range(6, 14)
 DIAG_EX2, DIAG_EY2, DIAG_EZ2, DIAG_ENERGY = 1, 2, 4, 8
@@ -35,7 +37,7 @@ class Injector(ctypes.Structure):
                 ("thickness", ctypes.c_double), ("axis_x", ctypes.c_double),
                 ("axis_y", ctypes.c_double), ("ramp_a", ctypes.c_double),
                 ("ramp_b", ctypes.c_double), ("n_sectors", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("sector_amp", c_double_p),
+                ("polarization", ctypes.c_int32), ("sector_amp", c_double_p),
                 ("sector_phase", c_double_p)]
 
 
@@ -47,7 +49,8 @@ class Info(ctypes.Structure):
                 ("n_source", ctypes.c_int32 * 6), ("n_slots", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_zchunk", ctypes.c_int32), ("step", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("interior_cells", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("interior_cells", ctypes.c_int64),
+                ("frame", ctypes.c_int32), ("xalign", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -99,6 +102,7 @@ _SIGS = {
     "fdtd_set_tile": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]),
+    "fdtd_set_frame": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),

@@ -28,12 +28,13 @@ class Batch:
                               cpml_grade=w.grade, cpml_sigma_scale=w.sigma_scale,
                               cpml_kappa_max=w.kappa_max, cpml_alpha_max=w.alpha_max,
                               kernel=L.KERNEL_SPLIT, reserved=0, stream=None)
+            kind, ra, rb = w.ramp_args
             injs[q] = L.Injector(wavelength=W.WAVELENGTH, theta=w.theta, order=w.order,
-                                 ramp_kind=L.RAMP_SIN2, e0=w.e0,
+                                 ramp_kind=kind, e0=w.e0,
                                  r_outer=w.r_outer_cells * w.dx,
                                  thickness=w.thickness_cells * w.dx, axis_x=math.nan,
-                                 axis_y=math.nan, ramp_a=w.ramp_seconds, ramp_b=0.0,
-                                 n_sectors=0, reserved=0)
+                                 axis_y=math.nan, ramp_a=ra, ramp_b=rb,
+                                 n_sectors=0, polarization=w.polarization)
             shapes.append((w.nx, w.ny, nz, npml, w.dx, w.dx, dz))
         b = ctypes.c_void_p()
         rc = self._lib.fdtd_batch_create(n, grids, injs if inject else None, stream,

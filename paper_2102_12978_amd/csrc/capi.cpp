@@ -416,6 +416,8 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->kernel = c->kernel;
     out->tile_rows = c->rows;
     out->tile_zchunk = c->zchunk;
+    out->frame = c->frame;
+    out->xalign = c->xalign;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
     const Frame fr = interior_of(c);
@@ -427,6 +429,8 @@ int fdtd_analytic_ey2(fdtd_ctx* c, float* host_out, int64_t n) {
     if (!c) return FDTD_EINVAL;
     return guarded(c, [&] {
         need(c->has_inj, "no injector", FDTD_ESTATE);
+        need(c->ant.polarization == FDTD_POL_X_TE,
+             "the analytic E_y intensity is that of the Pi_x TE beam", FDTD_ESTATE);
         const Problem& p = c->p;
         need(host_out && n >= (int64_t)p.nx * p.ny, "output buffer too small");
         const Antenna& a = c->ant;
@@ -456,6 +460,22 @@ int fdtd_set_tile(fdtd_ctx* c, int32_t rows, int32_t zchunk) {
     });
 }
 
+int fdtd_set_frame(fdtd_ctx* c, int32_t kind, int32_t xalign) {
+    if (!c) return FDTD_EINVAL;
+    if (c->batch_owned) {
+        c->err = "instance is stepped by its batch";
+        return FDTD_ESTATE;
+    }
+    return guarded(c, [&] {
+        need(kind == FDTD_FRAME_SPLIT || kind == FDTD_FRAME_FUSED,
+             "kind must be FDTD_FRAME_SPLIT or FDTD_FRAME_FUSED");
+        need(xalign == 32 || xalign == 64, "xalign must be 32 or 64");
+        c->frame = kind;
+        c->xalign = xalign;
+        ensure_partials(c);
+    });
+}
+
 int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                   int32_t* best_zchunk) {
     if (!c) return FDTD_EINVAL;
@@ -480,36 +500,44 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         check(hipEventCreate(&e0), "event");
         check(hipEventCreate(&e1), "event");
         float best = 1e30f;
-        int br = c->rows, bz = c->zchunk;
-        const int keep_rows = c->rows, keep_z = c->zchunk;
+        int br = c->rows, bz = c->zchunk, bf = c->frame, ba = c->xalign;
         LaunchTimer* keep_timer = c->timer;
         c->timer = nullptr;
-        for (int rows : {4, 8}) {
-            for (int cz : chunks) {
-                c->rows = rows;
-                c->zchunk = cz;
-                check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
-                check(hipEventRecord(e0, c->stream), "event");
-                for (int s = 0; s < steps_per_trial; ++s)
+        const int frames[3][2] = {{FDTD_FRAME_SPLIT, 32}, {FDTD_FRAME_FUSED, 32},
+                                  {FDTD_FRAME_FUSED, 64}};
+        for (const auto& fa : frames) {
+            for (int rows : {4, 8}) {
+                for (int cz : chunks) {
+                    c->frame = fa[0];
+                    c->xalign = fa[1];
+                    c->rows = rows;
+                    c->zchunk = cz;
+                    ensure_frame_tiles(c);
                     check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
-                check(hipEventRecord(e1, c->stream), "event");
-                check(hipEventSynchronize(e1), "event");
-                float ms = 0.f;
-                check(hipEventElapsedTime(&ms, e0, e1), "event");
-                if (ms < best) {
-                    best = ms;
-                    br = rows;
-                    bz = cz;
+                    check(hipEventRecord(e0, c->stream), "event");
+                    for (int s = 0; s < steps_per_trial; ++s)
+                        check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
+                    check(hipEventRecord(e1, c->stream), "event");
+                    check(hipEventSynchronize(e1), "event");
+                    float ms = 0.f;
+                    check(hipEventElapsedTime(&ms, e0, e1), "event");
+                    if (ms < best) {
+                        best = ms;
+                        br = rows;
+                        bz = cz;
+                        bf = fa[0];
+                        ba = fa[1];
+                    }
                 }
             }
         }
-        c->rows = keep_rows;
-        c->zchunk = keep_z;
         c->timer = static_cast<EventTimer*>(keep_timer);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         c->rows = br;
         c->zchunk = bz;
+        c->frame = bf;
+        c->xalign = ba;
         ensure_partials(c);
         if (best_rows) *best_rows = br;
         if (best_zchunk) *best_zchunk = bz;

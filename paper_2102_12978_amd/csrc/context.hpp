@@ -99,6 +99,12 @@ struct fdtd_ctx {
     int parity = 0;
     int kernel = FDTD_KERNEL_FUSED;
     int rows = 4, zchunk = 0;
+    // frame around the fused interior: split kernels, or fused boundary tiles
+    int frame = FDTD_FRAME_SPLIT;
+    int xalign = 32;                // interior x origin multiple (32 or 64 cells)
+    int4* ftiles = nullptr;         // fused frame tiles (0, x0, y0, z chunk)
+    int nftiles = 0, ftile_cap = 0, fblocks = 0, fcz = 0;
+    bfdtd::Frame ftile_rect{0, 0, 0, 0};
     bool batch_owned = false;      // stepped by an fdtd_batch
     EventTimer* timer = nullptr;
     std::string err;
@@ -185,23 +191,67 @@ inline void ensure_time_tables(fdtd_ctx* c, long long upto) {
     c->p.tH = c->tH;
 }
 
-// A fused step: the interior kernel, then the split kernels on the frame
-// around it (the whole grid when there is no interior or for the split
-// kernel choice).
+// A fused step: the interior kernel, then the frame around it, either by the
+// split kernels (the whole grid when there is no interior or for the split
+// kernel choice) or by one launch of the fused boundary-tile kernel.
 inline Frame interior_of(const fdtd_ctx* c) {
     if (c->kernel == FDTD_KERNEL_SPLIT) return Frame{0, 0, 0, 0};
-    return fused_interior_rect(c->p, c->rows);
+    return fused_interior_rect(c->p, c->rows, c->xalign);
+}
+
+// (the fused boundary tiles know walls and CPML but not the periodic test mode)
+inline bool frame_fused(const fdtd_ctx* c) {
+    return c->kernel != FDTD_KERNEL_SPLIT && c->frame == FDTD_FRAME_FUSED && !c->p.periodic;
 }
 
 inline int interior_partials(const fdtd_ctx* c) {
-    return c->kernel == FDTD_KERNEL_SPLIT ? 0 : fused_interior_tiles(c->p, c->rows, c->zchunk);
+    return c->kernel == FDTD_KERNEL_SPLIT ? 0
+                                          : fused_interior_tiles(c->p, c->rows, c->zchunk, c->xalign);
 }
 
+inline int frame_cz(const fdtd_ctx* c) { return c->zchunk > 0 ? c->zchunk : 16; }
+
 inline int partial_count(const fdtd_ctx* c) {
-    return interior_partials(c) + split_partial_count(c->p, interior_of(c));
+    const int fp = frame_fused(c) ? c->nftiles : split_partial_count(c->p, interior_of(c));
+    return interior_partials(c) + fp;
+}
+
+// Tile list of the fused frame: every 64 x 4 tile (x0 a multiple of 64, y0 of
+// BND_ROWS) that holds a grid cell outside the interior, per z chunk.
+inline void ensure_frame_tiles(fdtd_ctx* c) {
+    if (!frame_fused(c)) return;
+    const Frame fr = interior_of(c);
+    const int cz = std::min(frame_cz(c), c->p.nz);
+    if (c->ftiles && cz == c->fcz && fr.x0 == c->ftile_rect.x0 && fr.x1 == c->ftile_rect.x1 &&
+        fr.y0 == c->ftile_rect.y0 && fr.y1 == c->ftile_rect.y1)
+        return;
+    const Problem& p = c->p;
+    std::vector<int4> t;
+    for (int ch = 0; ch * cz < p.nz; ++ch)
+        for (int y0 = 0; y0 < p.ny; y0 += BND_ROWS)
+            for (int x0 = 0; x0 < p.nx; x0 += 64) {
+                const bool inside = x0 >= fr.x0 && x0 + 64 <= fr.x1 && y0 >= fr.y0 &&
+                                    y0 + BND_ROWS <= fr.y1;
+                if (!inside) t.push_back(make_int4(0, x0, y0, ch));
+            }
+    check(hipStreamSynchronize(c->stream), "sync");   // the old list may be in use
+    if ((int)t.size() > c->ftile_cap) {
+        dfree(c, c->ftiles);
+        c->ftiles = dalloc<int4>(c, t.size());
+        c->ftile_cap = (int)t.size();
+    }
+    check(hipMemcpy(c->ftiles, t.data(), t.size() * sizeof(int4), hipMemcpyHostToDevice),
+          "copy frame tiles");
+    c->nftiles = (int)t.size();
+    c->fcz = cz;
+    c->ftile_rect = fr;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    c->fblocks = std::max(1, std::min((c->nftiles + 3) / 4, cus * fused_bnd_blocks_per_cu()));
 }
 
 inline void ensure_partials(fdtd_ctx* c) {
+    ensure_frame_tiles(c);
     int need_n = std::max(1, partial_count(c));
     if (need_n <= c->epart_cap) return;
     check(hipStreamSynchronize(c->stream), "sync");
@@ -215,10 +265,18 @@ inline hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, 
     const Frame fr = interior_of(c);
     int off = 0;
     if (fr.x1 > fr.x0) {
-        hipError_t e = launch_fused_interior(q, n, parity, c->rows, c->zchunk, epart, c->stream,
-                                             c->timer);
+        hipError_t e = launch_fused_interior(q, n, parity, c->rows, c->zchunk, c->xalign, epart,
+                                             c->stream, c->timer);
         if (e != hipSuccess) return e;
         off = interior_partials(c);
+    }
+    if (frame_fused(c)) {
+        if (c->timer) c->timer->mark("frame_fused");
+        hipError_t e = launch_fused_bnd(q, nullptr, c->ftiles, c->nftiles, c->fcz, c->fblocks,
+                                        nullptr, n, parity, 1, fr, epart ? epart + off : nullptr,
+                                        c->stream);
+        if (c->timer) c->timer->mark(nullptr);
+        return e;
     }
     return launch_split_frame(q, n, parity, fr, epart ? epart + off : nullptr, c->stream,
                               c->timer);

@@ -74,6 +74,7 @@ struct Antenna {
     double ramp_a = 0, ramp_b = 0;       // normalised time units
     double e0 = 1;
     int order = 0;
+    int polarization = FDTD_POL_X_TE;
     double theta = 0;
     double ax = 0, ay = 0, r_in = 0, r_out = 0;
     int n_sectors = 0;
@@ -116,11 +117,12 @@ struct Frame {
     int x0, x1, y0, y1;
 };
 
-// Fused interior kernel (kernels_fused.hip); rows per wavefront: 4 or 8.
-Frame fused_interior_rect(const Problem& p, int rows);
-int fused_interior_tiles(const Problem& p, int rows, int zchunk);
+// Fused interior kernel (kernels_fused.hip); rows per wavefront: 4 or 8;
+// xalign: the interior starts on a multiple of 32 or 64 cells in x.
+Frame fused_interior_rect(const Problem& p, int rows, int xalign);
+int fused_interior_tiles(const Problem& p, int rows, int zchunk, int xalign);
 hipError_t launch_fused_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
-                                 double* epart, hipStream_t s, LaunchTimer* timer);
+                                 int xalign, double* epart, hipStream_t s, LaunchTimer* timer);
 
 // Split kernels over the frame around a rectangle (kernels_split.hip)
 long long frame_columns(const Problem& p, const Frame& fr);

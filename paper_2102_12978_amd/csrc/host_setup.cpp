@@ -106,6 +106,38 @@ void time_factor(const Antenna& a, double t, double* re, double* im) {
     *im = f * std::sin(ph);
 }
 
+// Q = ∇×Π and R = ∇×Q of the potential J_m(K r) e^{imφ} e^{iβz} carried
+// along x, y or z (pot 0, 1, 2), in the Cartesian forms printed in §3.1,
+// without the common factor e^{iβz}.
+void qr_fields(int pot, int m, double K, double beta, double k, double kr, double phi,
+               std::complex<double> q[3], std::complex<double> r[3]) {
+    const std::complex<double> I(0.0, 1.0);
+    auto u = [&](int nu) { return bessel_term(nu, kr, phi); };
+    const double kk = 0.5 * (k * k + beta * beta), k4 = 0.25 * K * K, bk = 0.5 * beta * K;
+    if (pot == 0) {
+        q[0] = 0.0;
+        q[1] = I * beta * u(m);
+        q[2] = (K / (2.0 * I)) * (u(m + 1) + u(m - 1));
+        r[0] = kk * u(m) + k4 * (u(m + 2) + u(m - 2));
+        r[1] = I * k4 * (u(m - 2) - u(m + 2));
+        r[2] = I * bk * (u(m - 1) - u(m + 1));
+    } else if (pot == 1) {
+        q[0] = -I * beta * u(m);
+        q[1] = 0.0;
+        q[2] = -0.5 * K * (u(m + 1) - u(m - 1));
+        r[0] = I * k4 * (u(m - 2) - u(m + 2));
+        r[1] = kk * u(m) - k4 * (u(m + 2) + u(m - 2));
+        r[2] = -bk * (u(m + 1) + u(m - 1));
+    } else {
+        q[0] = I * (0.5 * K) * (u(m + 1) + u(m - 1));
+        q[1] = 0.5 * K * (u(m + 1) - u(m - 1));
+        q[2] = 0.0;
+        r[0] = -I * bk * (u(m + 1) - u(m - 1));
+        r[1] = -bk * (u(m + 1) + u(m - 1));
+        r[2] = K * K * u(m);
+    }
+}
+
 std::string build_antenna(const fdtd_grid& g, int /*pitch*/, double ry, double rz,
                           const fdtd_injector& inj, Antenna* out) {
     Antenna a;
@@ -119,6 +151,8 @@ std::string build_antenna(const fdtd_grid& g, int /*pitch*/, double ry, double r
     if (inj.ramp_kind == FDTD_RAMP_GAUSS && !(inj.ramp_a > 0)) return "gauss ramp needs ramp_a > 0";
     if (inj.ramp_kind < FDTD_RAMP_SIN2 || inj.ramp_kind > FDTD_RAMP_CW) return "unknown ramp_kind";
     if (inj.n_sectors < 0) return "n_sectors must be >= 0";
+    if (inj.polarization < FDTD_POL_X_TE || inj.polarization > FDTD_POL_Z_TM)
+        return "polarization must be one of FDTD_POL_*";
     if (inj.n_sectors > 0 && (!inj.sector_amp || !inj.sector_phase))
         return "sector arrays required when n_sectors > 0";
 
@@ -158,6 +192,9 @@ std::string build_antenna(const fdtd_grid& g, int /*pitch*/, double ry, double r
     const bool walls = g.bc_xy != FDTD_BC_PERIODIC;
     const int m = inj.order;
     const double k = a.k, K = a.kr, beta = a.beta, e0 = inj.e0;
+    const int pot = inj.polarization % 3;              // potential along x, y, z
+    const bool tm = inj.polarization >= FDTD_POL_X_TM;  // E from R (TM) or from Q (TE)
+    a.polarization = inj.polarization;
     for (int j = 0; j < g.ny; ++j) {
         for (int i = 0; i < g.nx; ++i) {
             double bre[6] = {0}, bim[6] = {0};
@@ -172,29 +209,14 @@ std::string build_antenna(const fdtd_grid& g, int /*pitch*/, double ry, double r
                 if (!(r > a.r_in && r <= a.r_out)) continue;
                 double phi = std::atan2(y, x);
                 double kr = K * r;
-                std::complex<double> v;
+                std::complex<double> q[3], rr[3];
+                qr_fields(pot, m, K, beta, k, kr, phi, q, rr);
                 const std::complex<double> I(0.0, 1.0);
-                switch (c) {
-                    case EX: v = 0.0; break;
-                    case EY: v = -(e0 * beta / k) * bessel_term(m, kr, phi); break;
-                    case EZ:
-                        v = (e0 * K / (2.0 * k)) *
-                            (bessel_term(m + 1, kr, phi) + bessel_term(m - 1, kr, phi));
-                        break;
-                    case HX:
-                        v = (e0 / (k * k)) *
-                            (0.5 * (k * k + beta * beta) * bessel_term(m, kr, phi) +
-                             0.25 * K * K * (bessel_term(m + 2, kr, phi) + bessel_term(m - 2, kr, phi)));
-                        break;
-                    case HY:
-                        v = (e0 / (k * k)) * (0.25 * K * K * I) *
-                            (bessel_term(m - 2, kr, phi) - bessel_term(m + 2, kr, phi));
-                        break;
-                    default:  // HZ
-                        v = (e0 / (k * k)) * (0.5 * beta * K * I) *
-                            (bessel_term(m - 1, kr, phi) - bessel_term(m + 1, kr, phi));
-                        break;
-                }
+                std::complex<double> v;
+                if (c < 3)
+                    v = tm ? (e0 / (k * k)) * rr[c] : (I * e0 / k) * q[c];
+                else
+                    v = tm ? (-I * e0 / k) * q[c - 3] : (e0 / (k * k)) * rr[c - 3];
                 bre[c] = v.real();
                 bim[c] = v.imag();
                 mem[c] = 1;

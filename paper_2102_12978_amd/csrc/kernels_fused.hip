@@ -382,15 +382,16 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
     }
 }
 
-// Interior: x0 - 1 >= m and every x0 on a 128-byte line; the last segment
-// keeps its column x0 + 64 inside too; rows j0 - 1 .. j0 + TY likewise,
-// m = max(npml, 1), upper bound n - npml - 1.
-Interior interior(const Problem& p, int rows, int zchunk) {
+// Interior: x0 - 1 >= m and every x0 a multiple of xalign floats (32: a
+// 128-byte line; 64: whole 64-cell tiles of the frame kernel to the left);
+// the last segment keeps its column x0 + 64 inside too; rows j0 - 1 ..
+// j0 + TY likewise, m = max(npml, 1), upper bound n - npml - 1.
+Interior interior(const Problem& p, int rows, int zchunk, int xalign) {
     Interior I{0, 0, 0, 0, 0, 0};
     if (p.periodic) return I;
     const int m = p.npml > 0 ? p.npml : 1;
     const int hi_x = p.nx - p.npml - 1, hi_y = p.ny - p.npml - 1;
-    I.x_org = (m + 1 + 31) / 32 * 32;
+    I.x_org = (m + 1 + xalign - 1) / xalign * xalign;
     I.y_org = m + 1;
     I.nseg = hi_x - I.x_org - SEG + 1 >= 0 ? (hi_x - I.x_org - SEG) / SEG + 1 : 0;
     I.nrow = hi_y - I.y_org - rows + 1 >= 0 ? (hi_y - I.y_org - rows) / rows + 1 : 0;
@@ -405,9 +406,9 @@ int group_count(const Interior& I) {
 }
 
 template <int TY>
-hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, double* epart,
-                       hipStream_t s, LaunchTimer* timer) {
-    const Interior I = interior(p, TY, zchunk);
+hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, int xalign,
+                       double* epart, hipStream_t s, LaunchTimer* timer) {
+    const Interior I = interior(p, TY, zchunk, xalign);
     const int nb = group_count(I);
     if (nb <= 0) return hipSuccess;
     const int nbp = (nb + 7) / 8 * 8;
@@ -419,20 +420,21 @@ hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, do
 
 }  // namespace
 
-Frame fused_interior_rect(const Problem& p, int rows) {
-    const Interior I = interior(p, rows, 0);
+Frame fused_interior_rect(const Problem& p, int rows, int xalign) {
+    const Interior I = interior(p, rows, 0, xalign);
     if (I.nseg <= 0) return Frame{0, 0, 0, 0};
     return Frame{I.x_org, I.x_org + SEG * I.nseg, I.y_org, I.y_org + rows * I.nrow};
 }
 
-int fused_interior_tiles(const Problem& p, int rows, int zchunk) {
-    return group_count(interior(p, rows, zchunk)) * WAVES;
+int fused_interior_tiles(const Problem& p, int rows, int zchunk, int xalign) {
+    return group_count(interior(p, rows, zchunk, xalign)) * WAVES;
 }
 
 hipError_t launch_fused_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
-                                 double* epart, hipStream_t s, LaunchTimer* timer) {
-    if (rows == 4) return launch_rows<4>(p, n, parity, zchunk, epart, s, timer);
-    if (rows == 8) return launch_rows<8>(p, n, parity, zchunk, epart, s, timer);
+                                 int xalign, double* epart, hipStream_t s, LaunchTimer* timer) {
+    if (xalign != 32 && xalign != 64) return hipErrorInvalidValue;
+    if (rows == 4) return launch_rows<4>(p, n, parity, zchunk, xalign, epart, s, timer);
+    if (rows == 8) return launch_rows<8>(p, n, parity, zchunk, xalign, epart, s, timer);
     return hipErrorInvalidValue;
 }
 

@@ -80,7 +80,8 @@ class Solver:
         kind, a, b = w.ramp_args
         self.set_injector(W.WAVELENGTH, w.theta, w.order, w.e0, w.r_outer_cells * w.dx,
                           w.thickness_cells * w.dx, ramp_kind=kind, ramp_a=a, ramp_b=b,
-                          sector_amp=sector_amp, sector_phase=sector_phase)
+                          sector_amp=sector_amp, sector_phase=sector_phase,
+                          polarization=w.polarization)
 
     # -- API --------------------------------------------------------------
     def close(self):
@@ -105,10 +106,12 @@ class Solver:
 
     def set_injector(self, wavelength, theta, order, e0, r_outer, thickness,
                      ramp_kind=L.RAMP_SIN2, ramp_a=0.0, ramp_b=0.0, axis_x=math.nan,
-                     axis_y=math.nan, sector_amp=None, sector_phase=None):
+                     axis_y=math.nan, sector_amp=None, sector_phase=None,
+                     polarization=L.POL_X_TE):
         inj = L.Injector(wavelength=wavelength, theta=theta, order=order, ramp_kind=ramp_kind,
                          e0=e0, r_outer=r_outer, thickness=thickness, axis_x=axis_x,
-                         axis_y=axis_y, ramp_a=ramp_a, ramp_b=ramp_b, n_sectors=0, reserved=0)
+                         axis_y=axis_y, ramp_a=ramp_a, ramp_b=ramp_b, n_sectors=0,
+                         polarization=polarization)
         keep = []
         if sector_amp is not None:
             a = np.ascontiguousarray(sector_amp, dtype=np.float64)
@@ -188,6 +191,9 @@ class Solver:
 
     def set_tile(self, rows, zchunk=0):
         self._c(self._lib.fdtd_set_tile(self._ctx, rows, zchunk))
+
+    def set_frame(self, kind, xalign=32):
+        self._c(self._lib.fdtd_set_frame(self._ctx, int(kind), int(xalign)))
 
     def profile(self, on=True):
         self._c(self._lib.fdtd_profile_enable(self._ctx, 1 if on else 0))

@@ -49,6 +49,7 @@ class Workload:
     kappa_max: float = 1.0
     window_periods: float = 5.0
     ramp_kind: int = RAMP_SIN2
+    polarization: int = 0              # potential axis (0 x, 1 y, 2 z) + 3 for TM
     pulse_t_fs: float = 0.0            # Gaussian envelope: T (fs)
     pulse_t0_fs: float = 0.0           # Gaussian envelope: peak time T0 (fs)
     extra: dict = field(default_factory=dict)

@@ -21,4 +21,4 @@ def oracle_injector(w: W.Workload, amp=None, phase=None, e0=None):
     return P.Injector(W.WAVELENGTH, w.theta, w.order, w.e0 if e0 is None else e0,
                       w.r_outer_cells * w.dx, w.thickness_cells * w.dx,
                       ramp_kind=kind, ramp_a=a, ramp_b=b,
-                      sector_amp=amp, sector_phase=phase)
+                      sector_amp=amp, sector_phase=phase, polarization=w.polarization)

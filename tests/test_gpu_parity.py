@@ -240,3 +240,75 @@ def test_source_linearity_on_gpu():
     assert rel < 1e-6
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("xalign,rows,zchunk", [(32, 4, 0), (64, 4, 7), (64, 8, 9), (32, 8, 16)])
+def test_fused_frame(xalign, rows, zchunk):
+    """The frame stepped by the fused boundary-tile kernel (one launch over
+    the 64 x 4 tiles that hold frame cells): 300×150, antenna across interior
+    and frame, z chunks that do not divide nz; against the oracle (fields and
+    CPML memories) and against the split-kernel frame."""
+    w = W.parity_mid()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=rows, zchunk=zchunk)
+    s.set_frame(L.FRAME_FUSED, xalign)
+    inf = s.info()
+    assert inf.frame == L.FRAME_FUSED and inf.xalign == xalign
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    r = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=rows, zchunk=zchunk)
+    r.step(w.steps)
+    rel = GC.rel_l2(s.fields(), [x.astype(np.float64) for x in r.fields()])
+    print(f"  fused frame vs split frame rel-L2 = {rel:.2e}", flush=True)
+    assert rel < 1e-5
+    s.close()
+    r.close()
+
+
+@pytest.mark.parametrize("maker", [W.config0, W.parity_small, W.parity_gauss])
+def test_fused_frame_small_grids(maker):
+    """Grids with no interior or a small one: the fused frame covers the
+    whole grid or a ragged ring (PEC walls, CPML corners, lanes past nx)."""
+    w = maker()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    s.set_frame(L.FRAME_FUSED, 64)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()
+
+
+def test_fused_frame_diagnostics_and_energy():
+    w = W.parity_mid()
+    g = cases.oracle_grid(w)
+    plane, wb = g.nz // 2, 25
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=9)
+    s.set_frame(L.FRAME_FUSED, 64)
+    s.set_diagnostics(plane, wb, L.DIAG_EX2 | L.DIAG_EY2 | L.DIAG_EZ2 | L.DIAG_ENERGY)
+    s.step(w.steps)
+    d = Y.Diag(plane=plane, window_begin=wb)
+    _, st = GC.oracle_run(w, w.steps, diag=d, energy=True)
+    for q, key in ((L.DIAG_EX2, "ex2"), (L.DIAG_EY2, "ey2"), (L.DIAG_EZ2, "ez2")):
+        rel = GC.rel_l2([s.fluence(q)], [d.mean(key)])
+        print(f"  {key} rel-L2 = {rel:.2e}", flush=True)
+        assert rel <= TOL
+    e = s.energy()
+    print(f"  energy {e:.9e} vs {d.energy[-1]:.9e}", flush=True)
+    assert abs(e - d.energy[-1]) <= 1e-4 * abs(d.energy[-1])
+    s.close()
+
+
+@pytest.mark.parametrize("pol,order", [(L.POL_Y_TE, 1), (L.POL_Z_TE, 0), (L.POL_X_TM, 2),
+                                       (L.POL_Y_TM, 1), (L.POL_Z_TM, 0), (L.POL_Z_TE, 2)])
+def test_polarisations(pol, order):
+    """The other potentials and pairings of §3.1 (Π_y, Π_z; TE and TM),
+    including the m = 0 azimuthal (Π_z TE) and radial (Π_z TM) beams, on the
+    300×150 grid with the antenna across interior and frame."""
+    from dataclasses import replace
+    w = replace(W.parity_mid(), polarization=pol, order=order,
+                name=f"p_300x150x24_pol{pol}_m{order}")
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=7)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    _compare(s, st, g)
+    s.close()

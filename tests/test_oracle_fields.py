@@ -173,3 +173,103 @@ def test_sin2_ramp_is_smooth_turn_on():
     ant = P.Antenna(k=1.0, beta=1.0, omega=1.0, ramp_kind=P.RAMP_SIN2, ramp_a=100.0)
     t = np.array([0.0, 50.0, 100.0, 150.0])
     np.testing.assert_allclose(P.envelope(ant, t), [0.0, 0.5, 1.0, 1.0], atol=1e-15)
+
+
+def _pot_fd(axis, m, k, theta):
+    """Components of Π = ê_axis J_m e^{imφ} e^{iβz} as functions of a point."""
+    def psi(p):
+        return complex(F.hertz_x(m, k, theta, p[0], p[1], p[2]))
+
+    def zero(p):
+        return 0.0
+    return [psi if c == axis else zero for c in range(3)]
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_printed_q_r_of_pi_y_and_pi_z_are_curls(axis, m):
+    """Q and R printed for Π_y and Π_z (§3.1) are ∇×Π and ∇×Q."""
+    k = 2 * math.pi / 20.0
+    theta = math.radians(25.0)
+    beta = k * math.cos(theta)
+
+    def comp(which, ci):
+        def f(p):
+            qr = F.QR[axis](m, k, theta, np.array([p[0]]), np.array([p[1]]))[which]
+            return complex(np.asarray(qr[ci]).reshape(-1)[0]) * np.exp(1j * beta * p[2])
+        return f
+
+    pot = _pot_fd(axis, m, k, theta)
+    rng = np.random.default_rng(13 + axis)
+    h = 0.02
+    for p in [rng.uniform(-30, 30, 3) for _ in range(5)]:
+        q_fd = _curl(*pot, p, h)
+        q = np.array([comp(0, c)(p) for c in range(3)])
+        r_fd = _curl(comp(0, 0), comp(0, 1), comp(0, 2), p, h)
+        r = np.array([comp(1, c)(p) for c in range(3)])
+        assert np.linalg.norm(q_fd - q) / (k * np.linalg.norm(q) + 1e-30) < 1e-9
+        assert np.linalg.norm(r_fd - r) / (k * np.linalg.norm(r) + 1e-30) < 1e-9
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("tm", [0, 1])
+@pytest.mark.parametrize("m", [0, 1, 3])
+def test_every_mode_satisfies_maxwell(axis, tm, m):
+    """TE and TM pairings of the three potentials: curl E = i k H,
+    curl H = -i k E, div E = div H = 0."""
+    k = 2 * math.pi / 16.0
+    theta = math.radians(22.0)
+    beta = k * math.cos(theta)
+
+    def comp(ci):
+        def f(p):
+            a = F.amplitudes(axis, tm, m, k, theta, 0.7, np.array([p[0]]), np.array([p[1]]))[ci]
+            return complex(np.asarray(a).reshape(-1)[0]) * np.exp(1j * beta * p[2])
+        return f
+    ex, ey, ez, hx, hy, hz = [comp(c) for c in range(6)]
+    rng = np.random.default_rng(31 + 3 * axis + tm)
+    h = 0.02
+    for p in [rng.uniform(-35, 35, 3) for _ in range(4)]:
+        e = np.array([f(p) for f in (ex, ey, ez)])
+        hh = np.array([f(p) for f in (hx, hy, hz)])
+        scale = k * (np.linalg.norm(e) + np.linalg.norm(hh)) + 1e-6 * k
+        assert np.linalg.norm(_curl(ex, ey, ez, p, h) - 1j * k * hh) / scale < 1e-9
+        assert np.linalg.norm(_curl(hx, hy, hz, p, h) + 1j * k * e) / scale < 1e-9
+        assert abs(_div(ex, ey, ez, p, h)) / scale < 1e-9
+        assert abs(_div(hx, hy, hz, p, h)) / scale < 1e-9
+
+
+def test_pi_z_order0_is_radial_tm_and_azimuthal_te():
+    """§3.1: Π_z gives purely radial (TM, E from R) or azimuthal (TE, E from
+    Q) polarisation for m = 0."""
+    k = 2 * math.pi / 20.0
+    theta = math.radians(25.0)
+    rng = np.random.default_rng(17)
+    x, y = rng.uniform(-60, 60, 40), rng.uniform(-60, 60, 40)
+    phi = np.arctan2(y, x)
+    ex, ey, ez = F.amplitudes(2, 1, 0, k, theta, 1.0, x, y)[:3]
+    e_phi = -np.sin(phi) * ex + np.cos(phi) * ey
+    assert np.max(np.abs(e_phi)) < 1e-15 * max(1.0, np.max(np.abs(ex)))
+    assert np.max(np.abs(ex) + np.abs(ey)) > 1e-3
+    ex, ey, ez = F.amplitudes(2, 0, 0, k, theta, 1.0, x, y)[:3]
+    e_r = np.cos(phi) * ex + np.sin(phi) * ey
+    assert np.max(np.abs(e_r)) < 1e-15 and np.max(np.abs(ez)) == 0.0
+    assert np.max(np.abs(ex) + np.abs(ey)) > 1e-3
+
+
+@pytest.mark.parametrize("tm", [0, 1])
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_pi_y_is_pi_x_turned_by_a_quarter(tm, m):
+    """Turning Π_x by +90° about z gives e^{-imπ/2} Π_y, so every field of
+    Π_y is the turned field of Π_x times e^{imπ/2}."""
+    k = 2 * math.pi / 18.0
+    theta = math.radians(20.0)
+    rng = np.random.default_rng(19)
+    x, y = rng.uniform(-50, 50, 30), rng.uniform(-50, 50, 30)
+    fy = F.amplitudes(1, tm, m, k, theta, 1.0, x, y)
+    fx = F.amplitudes(0, tm, m, k, theta, 1.0, y, -x)      # at R^{-1} p
+    ph = np.exp(1j * m * math.pi / 2)
+    for o in (0, 3):   # E then H: (vx, vy, vz) -> (-vy, vx, vz)
+        np.testing.assert_allclose(fy[o + 0], -ph * fx[o + 1], atol=1e-14)
+        np.testing.assert_allclose(fy[o + 1], ph * fx[o + 0], atol=1e-14)
+        np.testing.assert_allclose(fy[o + 2], ph * fx[o + 2], atol=1e-14)
