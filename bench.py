@@ -107,6 +107,7 @@ def batch_measure(torch, stream, steps=1000, warmup=20):
         chis.append(max(res["chi"][:3]) if res["chi"] else float("nan"))
     b.close()
     value = inf.cells * steps / (ms * 1e-3) / 1e9
+    seq = sequential_measure(torch, stream, ws, steps=200)
     achieved = BYTES_PER_CELL * inf.cells * steps / (ms * 1e-3) / 1e9
     finite = [c for c in chis if c == c]
     return {
@@ -119,12 +120,41 @@ def batch_measure(torch, stream, steps=1000, warmup=20):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "bytes_per_cell": BYTES_PER_CELL},
+        "single_instance_runs": seq,
+        "batch_over_single": round(value / seq["value"], 3),
         "analytic_chi_central_lobes": {
             "median_percent": round(100 * float(sorted(finite)[len(finite) // 2]), 2)
             if finite else None,
             "max_percent": round(100 * max(finite), 2) if finite else None,
             "note": "report only: thin 2-cell antennas, window after 1020 steps"},
     }
+
+
+def sequential_measure(torch, stream, ws, steps=200, warmup=20):
+    """The same 64 problems stepped one after another as plain single-domain
+    forwards (fused kernel, autotuned tile and frame), for comparison with
+    the batched launch: summed step time of each instance."""
+    from paper_2102_12978_amd import _lib as L
+    from paper_2102_12978_amd.solver import Solver
+    total_ms, cells = 0.0, 0
+    for w in ws:
+        s = Solver.from_workload(w, kernel=L.KERNEL_FUSED, stream=stream.cuda_stream)
+        s.set_workload_injector(w)
+        s.autotune(2)
+        s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        total_ms += ev0.elapsed_time(ev1)
+        cells += s.nx * s.ny * s.nz
+        s.close()
+    return {"value": round(cells * steps / (total_ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
+            "steps_each": steps, "ms_per_step_all": round(total_ms / steps, 4)}
 
 
 def adjoint_measure(torch, stream):

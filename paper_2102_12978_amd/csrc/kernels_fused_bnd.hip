@@ -70,7 +70,11 @@ __device__ __forceinline__ void bhalo_slot(int q, int x0, int* c, int* r, int* x
     else { *c = HX; *r = q - 1; }
 }
 
-template <int TY>
+// MULTI: tiles of many instances (probs[instance]); otherwise of `single`.
+// Two instantiations keep every Problem access in one address space (the
+// kernel argument or global memory), so no generic pointer reaches the
+// per-cell code.
+template <int TY, bool MULTI>
 __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2)))
 fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* __restrict__ tiles,
                  int ntiles, int cz, const long long* __restrict__ nctr, long long n_off, int par,
@@ -81,7 +85,7 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int t = blockIdx.x * WAVES + w; t < ntiles; t += gridDim.x * WAVES) {
         const int4 tl = tiles[t];
-        const Problem& p = probs ? probs[tl.x] : single;
+        const Problem& p = MULTI ? probs[tl.x] : single;
         const int x0 = tl.y, j0 = tl.z;
         const int nx = p.nx, ny = p.ny, nz = p.nz;
         const int kb = tl.w * cz, ke = min(kb + cz, nz);
@@ -134,7 +138,10 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             bhalo_slot<TY>(lane, x0, &c, &r, &gx);
             const int y = j0 + r;
             gv = y >= 0 && y < ny && gx >= 0 && gx < nx;
-            gp = fo[c] + (size_t)min(max(y, 0), ny - 1) * p.pitch + min(max(gx, 0), nx - 1);
+            // offset from the parity base, not fo[c]: a per-lane index into fo[]
+            // would put the pointer array in scratch and make every load generic
+            gp = p.fbase[par] + (size_t)c * p.fstride + (size_t)min(max(y, 0), ny - 1) * p.pitch +
+                 min(max(gx, 0), nx - 1);
         }
         const size_t plane_elems = (size_t)ny * p.pitch;
         auto gather = [&](int kk) -> float {
@@ -367,17 +374,24 @@ hipError_t launch_fused_bnd(const Problem& single, const Problem* probs, const i
                             int ntiles, int cz, int blocks, const long long* nctr, long long n_off,
                             int par, int diag, const Frame& excl, double* epart, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fused_bnd_kernel<4>, dim3(blocks), dim3(64 * WAVES), 0, s, single, probs,
-                       tiles, ntiles, cz, nctr, n_off, par, diag, excl, epart);
+    if (probs)
+        hipLaunchKernelGGL((fused_bnd_kernel<4, true>), dim3(blocks), dim3(64 * WAVES), 0, s,
+                           single, probs, tiles, ntiles, cz, nctr, n_off, par, diag, excl, epart);
+    else
+        hipLaunchKernelGGL((fused_bnd_kernel<4, false>), dim3(blocks), dim3(64 * WAVES), 0, s,
+                           single, probs, tiles, ntiles, cz, nctr, n_off, par, diag, excl, epart);
     return hipGetLastError();
 }
 
 int fused_bnd_blocks_per_cu() {
-    int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<4>, 64 * WAVES, 0) !=
-        hipSuccess)
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, fused_bnd_kernel<4, true>, 64 * WAVES,
+                                                     0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<4, false>, 64 * WAVES,
+                                                     0) != hipSuccess)
         return 1;
-    return b > 0 ? b : 1;
+    const int m = a < b ? a : b;
+    return m > 0 ? m : 1;
 }
 
 }  // namespace bfdtd
