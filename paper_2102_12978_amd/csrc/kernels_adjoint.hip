@@ -34,8 +34,8 @@ struct Lam {
         return ((size_t)kk * p.ny + jj) * p.pitch + ii;
     }
     __device__ float v(int c, int ii, int jj, int kk) const { return f(c)[at(ii, jj, kk)]; }
-    __device__ const float* psi_old(int q) const { return pptr(p, par, q); }
-    __device__ float* psi_new(int q) const { return pptr(p, par ^ 1, q); }
+    __device__ gptr<const float> psi_old(int q) const { return pptr(p, par, q); }
+    __device__ gptr<float> psi_new(int q) const { return pptr(p, par ^ 1, q); }
 };
 
 // ---- H part transposed: λ_E += -D_b λ_Δ of the H terms ------------------

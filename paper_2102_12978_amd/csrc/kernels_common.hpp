@@ -7,6 +7,27 @@
 
 namespace bfdtd {
 
+// Every pointer in a Problem addresses device global memory. A Problem read
+// from memory (the batched kernels) holds them as generic pointers, which the
+// compiler would access with flat instructions; the accessors below return
+// them cast to the global address space, so every kernel emits global loads
+// and stores whichever way its Problem arrived.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> G(T* q) {
+    return (gptr<T>)q;
+}
+
+// float2 element i of a global array (HIP's float2 class cannot be copied
+// out of the global address space directly; one 8-byte load).
+__device__ __forceinline__ float2 ld2(gptr<const float2> q, size_t i) {
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = ((gptr<const v2f>)q)[i];
+    return make_float2(v.x, v.y);
+}
+
 // CPML slab index of an x position (-1 outside the slabs).
 __device__ __forceinline__ int slab_index(int i, int n, int npml) {
     if (npml <= 0) return -1;
@@ -23,20 +44,20 @@ __device__ __forceinline__ size_t psiy_at(const Problem& p, int k, int ys, int i
     return ((size_t)k * (2 * p.npml) + ys) * p.pitch + i;
 }
 
-__device__ __forceinline__ float* fptr(const Problem& p, int par, int c) {
-    return p.fbase[par] + c * p.fstride;
+__device__ __forceinline__ gptr<float> fptr(const Problem& p, int par, int c) {
+    return G(p.fbase[par]) + c * p.fstride;
 }
 
-__device__ __forceinline__ float* pptr(const Problem& p, int par, int q) {
-    return p.pbase[par] + psi_offset(p, q);
+__device__ __forceinline__ gptr<float> pptr(const Problem& p, int par, int q) {
+    return G(p.pbase[par]) + psi_offset(p, q);
 }
 
-__device__ __forceinline__ const float* cx_tab(const Problem& p, int t) {
-    return p.ctab + (size_t)t * p.nx;
+__device__ __forceinline__ gptr<const float> cx_tab(const Problem& p, int t) {
+    return G(p.ctab) + (size_t)t * p.nx;
 }
 
-__device__ __forceinline__ const float* cy_tab(const Problem& p, int t) {
-    return p.ctab + (size_t)6 * p.nx + (size_t)t * p.ny;
+__device__ __forceinline__ gptr<const float> cy_tab(const Problem& p, int t) {
+    return G(p.ctab) + (size_t)6 * p.nx + (size_t)t * p.ny;
 }
 
 // Re{a · b}

@@ -27,12 +27,12 @@ namespace {
 constexpr int SEG = 64;
 constexpr int WAVES = 4;
 
-__device__ __forceinline__ float ldb(const float* base, unsigned boff) {
-    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
+__device__ __forceinline__ float ldb(gptr<const float> base, unsigned boff) {
+    return *(gptr<const float>)((gptr<const char>)base + boff);
 }
 
-__device__ __forceinline__ void stb(float* base, unsigned boff, float v) {
-    __builtin_nontemporal_store(v, reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff));
+__device__ __forceinline__ void stb(gptr<float> base, unsigned boff, float v) {
+    __builtin_nontemporal_store(v, (gptr<float>)((gptr<char>)base + boff));
 }
 
 __device__ __forceinline__ float bcastb(float v, int q) {
@@ -93,12 +93,12 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
         const bool xin = x < nx;
         const int mask = (diag && n >= p.win_begin) ? p.diag_mask : 0;
         const unsigned pstride = 4u * (unsigned)(ny * p.pitch);
-        const float* fo[6];
-        float* fw[6];
+        gptr<const float> fo[6];
+        gptr<float> fw[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            fo[c] = p.fbase[par] + c * p.fstride;
-            fw[c] = p.fbase[par ^ 1] + c * p.fstride;
+            fo[c] = G(p.fbase[par]) + c * p.fstride;
+            fw[c] = G(p.fbase[par ^ 1]) + c * p.fstride;
         }
         // rows y0-1 .. y0+TY: byte offset (clamped into the grid) and validity
         unsigned ro[TY + 2];
@@ -121,17 +121,17 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
         int slot[TY + 1];
 #pragma unroll
         for (int r = 0; r <= TY; ++r)
-            slot[r] = (p.colmap && xin && rv[r + 1]) ? p.colmap[(size_t)(j0 + r) * nx + x] : -1;
+            slot[r] = (p.colmap && xin && rv[r + 1]) ? G(p.colmap)[(size_t)(j0 + r) * nx + x] : -1;
         // right halo column
         const bool hr = x0 + SEG < nx;              // E at x0+64 exists
         const bool hl = x0 > 0;                     // H at x0-1 exists
         int slot_h[TY];
 #pragma unroll
         for (int r = 0; r < TY; ++r)
-            slot_h[r] = (p.colmap && hr && j0 + r < ny) ? p.colmap[(size_t)(j0 + r) * nx + x0 + SEG]
+            slot_h[r] = (p.colmap && hr && j0 + r < ny) ? G(p.colmap)[(size_t)(j0 + r) * nx + x0 + SEG]
                                                         : -1;
         // gather slot of this lane
-        const float* gp = fo[0];
+        gptr<const float> gp = fo[0];
         bool gv = false;
         if (lane < H::COUNT) {
             int c, r, gx;
@@ -140,7 +140,7 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             gv = y >= 0 && y < ny && gx >= 0 && gx < nx;
             // offset from the parity base, not fo[c]: a per-lane index into fo[]
             // would put the pointer array in scratch and make every load generic
-            gp = p.fbase[par] + (size_t)c * p.fstride + (size_t)min(max(y, 0), ny - 1) * p.pitch +
+            gp = G(p.fbase[par]) + (size_t)c * p.fstride + (size_t)min(max(y, 0), ny - 1) * p.pitch +
                  min(max(gx, 0), nx - 1);
         }
         const size_t plane_elems = (size_t)ny * p.pitch;
@@ -163,9 +163,9 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
                          float (&ey)[TY + 1], float (&ez)[TY + 1]) {
             float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
             if (p.colmap) {
-                const float2 tt = p.tE[n];
-                pt0 = cmul(p.zph[2 * kk], tt);
-                pt1 = cmul(p.zph[2 * kk + 1], tt);
+                const float2 tt = ld2(G(p.tE), n);
+                pt0 = cmul(ld2(G(p.zph), 2 * kk), tt);
+                pt1 = cmul(ld2(G(p.zph), 2 * kk + 1), tt);
             }
 #pragma unroll
             for (int r = 0; r <= TY; ++r) {
@@ -198,9 +198,9 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
         auto e_right = [&](int kk, const float (&hy)[TY + 1], const float (&hz)[TY + 2], float g) {
             float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
             if (p.colmap) {
-                const float2 tt = p.tE[n];
-                pt0 = cmul(p.zph[2 * kk], tt);
-                pt1 = cmul(p.zph[2 * kk + 1], tt);
+                const float2 tt = ld2(G(p.tE), n);
+                pt0 = cmul(ld2(G(p.zph), 2 * kk), tt);
+                pt1 = cmul(ld2(G(p.zph), 2 * kk + 1), tt);
             }
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
@@ -241,10 +241,11 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
                 if (epart) en += (double)ex[r] * ex[r] + (double)ey[r] * ey[r] + (double)ez[r] * ez[r];
                 if (kk == p.plane) {
                     const size_t pl = (size_t)(j0 + r) * nx + x, ps = (size_t)nx * ny;
-                    if (mask & FDTD_DIAG_EX2) p.fl[pl] += (double)ex[r] * ex[r];
-                    if (mask & FDTD_DIAG_EY2) p.fl[ps + pl] += (double)ey[r] * ey[r];
-                    if (mask & FDTD_DIAG_EZ2) p.fl[2 * ps + pl] += (double)ez[r] * ez[r];
-                    if (p.rec) p.rec[(size_t)(n - p.rec_begin) * ps + pl] = ey[r];
+                    const gptr<double> fl = G(p.fl);
+                    if (mask & FDTD_DIAG_EX2) fl[pl] += (double)ex[r] * ex[r];
+                    if (mask & FDTD_DIAG_EY2) fl[ps + pl] += (double)ey[r] * ey[r];
+                    if (mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] += (double)ez[r] * ez[r];
+                    if (p.rec) G(p.rec)[(size_t)(n - p.rec_begin) * ps + pl] = ey[r];
                 }
             }
         };
@@ -288,7 +289,7 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             }
             store_e(kb, ex, ey, ez);
         }
-        const float2 th = p.colmap ? p.tH[n] : make_float2(0.f, 0.f);
+        const float2 th = p.colmap ? ld2(G(p.tH), n) : make_float2(0.f, 0.f);
 
         for (int k = kb; k < ke; ++k) {
             const int kn = k + 1 == nz ? 0 : k + 1;
@@ -317,8 +318,8 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             e_right(kn, hy, hz, gn);
             float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
             if (p.colmap) {
-                qt0 = cmul(p.zph[2 * k], th);
-                qt1 = cmul(p.zph[2 * k + 1], th);
+                qt0 = cmul(ld2(G(p.zph), 2 * k), th);
+                qt1 = cmul(ld2(G(p.zph), 2 * k + 1), th);
             }
 #pragma unroll
             for (int r = 0; r < TY; ++r) {

@@ -67,10 +67,10 @@ __device__ __forceinline__ void e_cell(const Problem& p, int par, int i, int j, 
     if (!hold_x) ey += p.sz * d_zhx - p.sx * tx_hz;
     if (!hold_x && !hold_y) ez += p.sx * tx_hy - p.sy * ty_hx;
     if (slot >= 0) {
-        const float2* a = p.amp + (size_t)slot * 6;
-        ex += cmul_re(a[EX], pt0);
-        ey += cmul_re(a[EY], pt0);
-        ez += cmul_re(a[EZ], pt1);
+        const gptr<const float2> a = G(p.amp) + (size_t)slot * 6;
+        ex += cmul_re(ld2(a, EX), pt0);
+        ey += cmul_re(ld2(a, EY), pt0);
+        ez += cmul_re(ld2(a, EZ), pt1);
     }
 }
 
@@ -119,10 +119,10 @@ __device__ __forceinline__ void h_cell(const Problem& p, int par, int i, int j, 
     hy -= p.sz * d_zex - p.sx * tx_ez;
     hz -= p.sx * tx_ey - p.sy * ty_ex;
     if (slot >= 0) {
-        const float2* a = p.amp + (size_t)slot * 6;
-        hx += cmul_re(a[HX], qt1);
-        hy += cmul_re(a[HY], qt1);
-        hz += cmul_re(a[HZ], qt0);
+        const gptr<const float2> a = G(p.amp) + (size_t)slot * 6;
+        hx += cmul_re(ld2(a, HX), qt1);
+        hy += cmul_re(ld2(a, HY), qt1);
+        hz += cmul_re(ld2(a, HZ), qt0);
     }
 }
 
@@ -131,8 +131,8 @@ __device__ __forceinline__ void h_cell(const Problem& p, int par, int i, int j, 
 // diag_mask. Returns |E^{n+1}|² at the cell (for the energy).
 __device__ __forceinline__ double e_point(const Problem& p, long long n, int par, int i, int j,
                                           int k, int diag_mask) {
-    auto fo = [&](int c) -> const float* { return fptr(p, par, c); };
-    auto fn = [&](int c) -> float* { return fptr(p, par ^ 1, c); };
+    auto fo = [&](int c) { return fptr(p, par, c); };
+    auto fn = [&](int c) { return fptr(p, par ^ 1, c); };
     const bool per = p.periodic != 0;
     const int km = k == 0 ? p.nz - 1 : k - 1;
     int im = i - 1, jm = j - 1;
@@ -154,12 +154,12 @@ __device__ __forceinline__ double e_point(const Problem& p, long long n, int par
     h.hy_km = fo(HY)[row_km + i];
     h.hx_km = fo(HX)[row_km + i];
     float ex = fo(EX)[id], ey = fo(EY)[id], ez = fo(EZ)[id];
-    const int slot = p.colmap ? p.colmap[(size_t)j * p.nx + i] : -1;
+    const int slot = p.colmap ? G(p.colmap)[(size_t)j * p.nx + i] : -1;
     float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
     if (slot >= 0) {
-        const float2 t = p.tE[n];
-        pt0 = cmul(p.zph[2 * k], t);
-        pt1 = cmul(p.zph[2 * k + 1], t);
+        const float2 t = ld2(G(p.tE), n);
+        pt0 = cmul(ld2(G(p.zph), 2 * k), t);
+        pt1 = cmul(ld2(G(p.zph), 2 * k + 1), t);
     }
     e_cell(p, par, i, j, k, h, ex, ey, ez, slot, pt0, pt1, true);
     fn(EX)[id] = ex;
@@ -167,11 +167,12 @@ __device__ __forceinline__ double e_point(const Problem& p, long long n, int par
     fn(EZ)[id] = ez;
     if (k == p.plane && diag_mask) {
         const size_t pl = (size_t)j * p.nx + i, ps = (size_t)p.nx * p.ny;
-        if (diag_mask & FDTD_DIAG_EX2) p.fl[pl] += (double)ex * ex;
-        if (diag_mask & FDTD_DIAG_EY2) p.fl[ps + pl] += (double)ey * ey;
-        if (diag_mask & FDTD_DIAG_EZ2) p.fl[2 * ps + pl] += (double)ez * ez;
+        const gptr<double> fl = G(p.fl);
+        if (diag_mask & FDTD_DIAG_EX2) fl[pl] += (double)ex * ex;
+        if (diag_mask & FDTD_DIAG_EY2) fl[ps + pl] += (double)ey * ey;
+        if (diag_mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] += (double)ez * ez;
     }
-    if (k == p.plane && p.rec) p.rec[(size_t)(n - p.rec_begin) * p.nx * p.ny + (size_t)j * p.nx + i] = ey;
+    if (k == p.plane && p.rec) G(p.rec)[(size_t)(n - p.rec_begin) * p.nx * p.ny + (size_t)j * p.nx + i] = ey;
     return (double)ex * ex + (double)ey * ey + (double)ez * ez;
 }
 
@@ -180,8 +181,8 @@ __device__ __forceinline__ double e_point(const Problem& p, long long n, int par
 // H^{n+1/2}·H^{n+3/2} at the cell (for the energy).
 __device__ __forceinline__ double h_point(const Problem& p, long long n, int par, int i, int j,
                                           int k) {
-    auto fo = [&](int c) -> const float* { return fptr(p, par, c); };
-    auto fn = [&](int c) -> float* { return fptr(p, par ^ 1, c); };   // E^{n+1} is here
+    auto fo = [&](int c) { return fptr(p, par, c); };
+    auto fn = [&](int c) { return fptr(p, par ^ 1, c); };   // E^{n+1} is here
     const bool per = p.periodic != 0;
     const int kp = k + 1 == p.nz ? 0 : k + 1;
     int ip = i + 1, jp = j + 1;
@@ -204,12 +205,12 @@ __device__ __forceinline__ double h_point(const Problem& p, long long n, int par
     e.ey_kp = fn(EY)[row_kp + i];
     const float hx0 = fo(HX)[id], hy0 = fo(HY)[id], hz0 = fo(HZ)[id];
     float hx = hx0, hy = hy0, hz = hz0;
-    const int slot = p.colmap ? p.colmap[(size_t)j * p.nx + i] : -1;
+    const int slot = p.colmap ? G(p.colmap)[(size_t)j * p.nx + i] : -1;
     float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
     if (slot >= 0) {
-        const float2 t = p.tH[n];
-        qt0 = cmul(p.zph[2 * k], t);
-        qt1 = cmul(p.zph[2 * k + 1], t);
+        const float2 t = ld2(G(p.tH), n);
+        qt0 = cmul(ld2(G(p.zph), 2 * k), t);
+        qt1 = cmul(ld2(G(p.zph), 2 * k + 1), t);
     }
     h_cell(p, par, i, j, k, e, hx, hy, hz, slot, qt0, qt1);
     fn(HX)[id] = hx;
