@@ -148,6 +148,8 @@ typedef struct fdtd_info {
     int64_t interior_cells;      /* cells per step updated by the fused kernel */
     int32_t frame;               /* FDTD_FRAME_* used around the interior     */
     int32_t xalign;              /* interior x origin multiple (32 or 64)     */
+    int32_t frame_rows;          /* rows per fused frame tile (2 or 4)        */
+    int32_t reserved;
 } fdtd_info;
 
 /* Library version string (static storage). */
@@ -240,14 +242,15 @@ int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
 /* How the fused kernel's frame (the CPML slabs, walls and the cells the
  * interior's tiles leave over) is stepped:
  *   FDTD_FRAME_SPLIT: the split E and H kernels, one thread per cell;
- *   FDTD_FRAME_FUSED: one launch of the fused step over the 64 x 4 tiles
- *     that hold frame cells, each cell through the same per-cell boundary
- *     code (bit-identical results), marching a z chunk like the interior.
+ *   FDTD_FRAME_FUSED: one launch of the fused step over the 64 x `rows`
+ *     tiles (rows 2 or 4) that hold frame cells, each cell through the same
+ *     per-cell boundary code as the split kernels, marching a z chunk like
+ *     the interior.
  * xalign (32 or 64) rounds the interior's x origin up to a multiple of that
  * many cells; 64 makes the frame's x strips whole tiles. */
 #define FDTD_FRAME_SPLIT 0
 #define FDTD_FRAME_FUSED 1
-int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign);
+int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
 
 /* Time candidate tile shapes and frame choices on the live problem (the state
  * is restored) and keep the fastest. *best_rows / *best_zchunk may be NULL. */
@@ -411,10 +414,10 @@ int fdtd_batch_step(fdtd_batch *b, int64_t nsteps);
 
 /* Step kernel: FDTD_KERNEL_SPLIT (default: an E launch and an H launch
  * over flattened columns) or FDTD_KERNEL_FUSED (one launch per step over
- * tiles of 64 x cells by 4 rows marching through a z chunk, the boundary
- * cases handled per cell; bit-identical to the split kernels). The
- * autotuner tries both. */
-int fdtd_batch_set_kernel(fdtd_batch *b, int32_t kernel);
+ * tiles of 64 x cells by `rows` rows (2 or 4; ignored by the split kernel)
+ * marching through a z chunk, the boundary cases handled per cell;
+ * bit-identical to the split kernels). The autotuner tries both. */
+int fdtd_batch_set_kernel(fdtd_batch *b, int32_t kernel, int32_t rows);
 
 /* Work-item shape: cols in {64, 128, 256} (split kernel only), zchunk >= 0
  * (z planes per work item, 0 = whole z). */

@@ -50,7 +50,8 @@ class Info(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_zchunk", ctypes.c_int32), ("step", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("interior_cells", ctypes.c_int64),
-                ("frame", ctypes.c_int32), ("xalign", ctypes.c_int32)]
+                ("frame", ctypes.c_int32), ("xalign", ctypes.c_int32),
+                ("frame_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -102,7 +103,7 @@ _SIGS = {
     "fdtd_set_tile": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]),
-    "fdtd_set_frame": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32]),
+    "fdtd_set_frame": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
@@ -127,7 +128,7 @@ _SIGS = {
     "fdtd_batch_step": (ctypes.c_int, [_BATCH, ctypes.c_int64]),
     "fdtd_batch_set_tile": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_batch_set_graph_steps": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
-    "fdtd_batch_set_kernel": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
+    "fdtd_batch_set_kernel": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_batch_autotune": (ctypes.c_int, [_BATCH, ctypes.c_int32, _I32P, _I32P]),
     "fdtd_batch_get_info": (ctypes.c_int, [_BATCH, ctypes.POINTER(BatchInfo)]),
     "fdtd_stream_probe": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,

@@ -74,8 +74,8 @@ class Batch:
     def set_tile(self, cols, zchunk=0):
         self._c(self._lib.fdtd_batch_set_tile(self._b, int(cols), int(zchunk)))
 
-    def set_kernel(self, kernel):
-        self._c(self._lib.fdtd_batch_set_kernel(self._b, int(kernel)))
+    def set_kernel(self, kernel, rows=2):
+        self._c(self._lib.fdtd_batch_set_kernel(self._b, int(kernel), int(rows)))
 
     def set_graph_steps(self, steps):
         self._c(self._lib.fdtd_batch_set_graph_steps(self._b, int(steps)))

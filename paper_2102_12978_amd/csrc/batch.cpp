@@ -23,6 +23,7 @@ struct fdtd_batch {
     int nwork = 0;
     int cols = 256, zchunk = 0, blocks = 0;
     int kernel = FDTD_KERNEL_SPLIT;    // split E/H passes, or fused boundary tiles
+    int bnd_rows = 2;                  // rows per fused boundary tile (2 or 4)
     int graph_steps = 20;              // even, so a replay leaves the parity unchanged
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // per starting parity
     int cu_count = 256;
@@ -73,7 +74,7 @@ int fused_cz(const fdtd_batch* b) { return b->zchunk > 0 ? b->zchunk : (1 << 30)
 // Work items. Split kernels: per instance, blocks of `cols` flattened (x, y)
 // columns (x running over the padded pitch) times z ranges of `zchunk`
 // planes (0: the whole z extent). Fused kernel: per instance and z chunk,
-// tiles of 64 x cells by BND_ROWS rows, x fastest so that consecutive tiles
+// tiles of 64 x cells by bnd_rows rows, x fastest so that consecutive tiles
 // are x-adjacent.
 void build_work(fdtd_batch* b) {
     std::vector<int4> w;
@@ -82,7 +83,7 @@ void build_work(fdtd_batch* b) {
         if (b->kernel == FDTD_KERNEL_FUSED) {
             const int cz = std::min(fused_cz(b), p.nz);
             for (int c = 0; c * cz < p.nz; ++c)
-                for (int y0 = 0; y0 < p.ny; y0 += BND_ROWS)
+                for (int y0 = 0; y0 < p.ny; y0 += b->bnd_rows)
                     for (int x0 = 0; x0 < p.nx; x0 += 64) w.push_back(make_int4(q, x0, y0, c));
             continue;
         }
@@ -104,7 +105,7 @@ void build_work(fdtd_batch* b) {
     check(hipMemcpy(b->work, w.data(), w.size() * sizeof(int4), hipMemcpyHostToDevice), "copy work");
     // persistent grid: as many workgroups as can be resident at once
     if (b->kernel == FDTD_KERNEL_FUSED) {
-        const int per_cu = fused_bnd_blocks_per_cu();
+        const int per_cu = fused_bnd_blocks_per_cu(b->bnd_rows, true);
         b->blocks = std::max(1, std::min((b->nwork + 3) / 4, b->cu_count * per_cu));
     } else {
         const int per_cu = batch_blocks_per_cu(b->cols);
@@ -135,8 +136,9 @@ void upload_problems(fdtd_batch* b, bool force = false) {
 
 hipError_t launch_pair(const fdtd_batch* b, hipStream_t s, int off, int par, int diag) {
     if (b->kernel == FDTD_KERNEL_FUSED)
-        return launch_fused_bnd(b->host_probs[0], b->probs, b->work, b->nwork, fused_cz(b),
-                                b->blocks, b->nctr, off, par, diag, Frame{0, 0, 0, 0}, nullptr, s);
+        return launch_fused_bnd(b->host_probs[0], b->probs, b->work, b->nwork, b->bnd_rows,
+                                fused_cz(b), b->blocks, b->nctr, off, par, diag,
+                                Frame{0, 0, 0, 0}, nullptr, s);
     hipError_t e = launch_batch_e(b->probs, b->work, b->nwork, b->cols, b->blocks, b->nctr, off,
                                   par, diag, s);
     if (e != hipSuccess) return e;
@@ -290,12 +292,14 @@ int fdtd_batch_set_tile(fdtd_batch* b, int32_t cols, int32_t zchunk) {
     });
 }
 
-int fdtd_batch_set_kernel(fdtd_batch* b, int32_t kernel) {
+int fdtd_batch_set_kernel(fdtd_batch* b, int32_t kernel, int32_t rows) {
     if (!b) return FDTD_EINVAL;
     return bguard(b, [&] {
         need(kernel == FDTD_KERNEL_FUSED || kernel == FDTD_KERNEL_SPLIT,
              "kernel must be FDTD_KERNEL_FUSED or FDTD_KERNEL_SPLIT");
+        need(rows == 2 || rows == 4, "rows must be 2 or 4");
         b->kernel = kernel;
+        b->bnd_rows = rows;
         build_work(b);
     });
 }
@@ -321,17 +325,19 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
         hipEvent_t e0, e1;
         check(hipEventCreate(&e0), "event");
         check(hipEventCreate(&e1), "event");
-        int bk = b->kernel, bc = b->cols, bz = b->zchunk;
+        int bk = b->kernel, bc = b->cols, bz = b->zchunk, br = b->bnd_rows;
         float best = -1.f;
-        struct Cand { int kernel, cols, zc; };
+        struct Cand { int kernel, cols, zc, rows; };
         std::vector<Cand> cands;
-        for (int zc : {0, 32, 16, 8}) cands.push_back({FDTD_KERNEL_FUSED, b->cols, zc});
+        for (int rows : {2, 4})
+            for (int zc : {0, 32, 16, 8}) cands.push_back({FDTD_KERNEL_FUSED, b->cols, zc, rows});
         for (int cols : {64, 128, 256})
-            for (int zc : {0, 16, 8, 4, 1}) cands.push_back({FDTD_KERNEL_SPLIT, cols, zc});
+            for (int zc : {0, 16, 8, 4, 1}) cands.push_back({FDTD_KERNEL_SPLIT, cols, zc, br});
         // Trials read the live parity and write the other one only, with the
         // plane accumulation off, so the state is left as it was.
         for (const Cand& cd : cands) {
             b->kernel = cd.kernel;
+            b->bnd_rows = cd.rows;
             b->cols = cd.cols;
             b->zchunk = cd.zc;
             build_work(b);
@@ -348,11 +354,13 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
                 bk = cd.kernel;
                 bc = cd.cols;
                 bz = cd.zc;
+                br = cd.rows;
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         b->kernel = bk;
+        b->bnd_rows = br;
         b->cols = bc;
         b->zchunk = bz;
         build_work(b);

@@ -418,6 +418,7 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->tile_zchunk = c->zchunk;
     out->frame = c->frame;
     out->xalign = c->xalign;
+    out->frame_rows = c->frame_rows;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
     const Frame fr = interior_of(c);
@@ -460,7 +461,7 @@ int fdtd_set_tile(fdtd_ctx* c, int32_t rows, int32_t zchunk) {
     });
 }
 
-int fdtd_set_frame(fdtd_ctx* c, int32_t kind, int32_t xalign) {
+int fdtd_set_frame(fdtd_ctx* c, int32_t kind, int32_t xalign, int32_t rows) {
     if (!c) return FDTD_EINVAL;
     if (c->batch_owned) {
         c->err = "instance is stepped by its batch";
@@ -470,8 +471,10 @@ int fdtd_set_frame(fdtd_ctx* c, int32_t kind, int32_t xalign) {
         need(kind == FDTD_FRAME_SPLIT || kind == FDTD_FRAME_FUSED,
              "kind must be FDTD_FRAME_SPLIT or FDTD_FRAME_FUSED");
         need(xalign == 32 || xalign == 64, "xalign must be 32 or 64");
+        need(rows == 2 || rows == 4, "rows must be 2 or 4");
         c->frame = kind;
         c->xalign = xalign;
+        c->frame_rows = rows;
         ensure_partials(c);
     });
 }
@@ -500,16 +503,18 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         check(hipEventCreate(&e0), "event");
         check(hipEventCreate(&e1), "event");
         float best = 1e30f;
-        int br = c->rows, bz = c->zchunk, bf = c->frame, ba = c->xalign;
+        int br = c->rows, bz = c->zchunk, bf = c->frame, ba = c->xalign, bfr = c->frame_rows;
         LaunchTimer* keep_timer = c->timer;
         c->timer = nullptr;
-        const int frames[3][2] = {{FDTD_FRAME_SPLIT, 32}, {FDTD_FRAME_FUSED, 32},
-                                  {FDTD_FRAME_FUSED, 64}};
+        const int frames[5][3] = {{FDTD_FRAME_SPLIT, 32, 2}, {FDTD_FRAME_FUSED, 32, 2},
+                                  {FDTD_FRAME_FUSED, 64, 2}, {FDTD_FRAME_FUSED, 32, 4},
+                                  {FDTD_FRAME_FUSED, 64, 4}};
         for (const auto& fa : frames) {
             for (int rows : {4, 8}) {
                 for (int cz : chunks) {
                     c->frame = fa[0];
                     c->xalign = fa[1];
+                    c->frame_rows = fa[2];
                     c->rows = rows;
                     c->zchunk = cz;
                     ensure_frame_tiles(c);
@@ -527,6 +532,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                         bz = cz;
                         bf = fa[0];
                         ba = fa[1];
+                        bfr = fa[2];
                     }
                 }
             }
@@ -538,6 +544,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         c->zchunk = bz;
         c->frame = bf;
         c->xalign = ba;
+        c->frame_rows = bfr;
         ensure_partials(c);
         if (best_rows) *best_rows = br;
         if (best_zchunk) *best_zchunk = bz;

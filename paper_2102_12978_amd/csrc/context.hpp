@@ -102,8 +102,9 @@ struct fdtd_ctx {
     // frame around the fused interior: split kernels, or fused boundary tiles
     int frame = FDTD_FRAME_SPLIT;
     int xalign = 32;                // interior x origin multiple (32 or 64 cells)
+    int frame_rows = 2;             // rows per fused frame tile (2 or 4)
     int4* ftiles = nullptr;         // fused frame tiles (0, x0, y0, z chunk)
-    int nftiles = 0, ftile_cap = 0, fblocks = 0, fcz = 0;
+    int nftiles = 0, ftile_cap = 0, fblocks = 0, fcz = 0, frows = 0;
     bfdtd::Frame ftile_rect{0, 0, 0, 0};
     bool batch_owned = false;      // stepped by an fdtd_batch
     EventTimer* timer = nullptr;
@@ -216,22 +217,25 @@ inline int partial_count(const fdtd_ctx* c) {
     return interior_partials(c) + fp;
 }
 
-// Tile list of the fused frame: every 64 x 4 tile (x0 a multiple of 64, y0 of
-// BND_ROWS) that holds a grid cell outside the interior, per z chunk.
+// Tile list of the fused frame: every 64 x frame_rows tile (x0 a multiple of
+// 64, y0 of frame_rows) that holds a grid cell outside the interior, per z
+// chunk.
 inline void ensure_frame_tiles(fdtd_ctx* c) {
     if (!frame_fused(c)) return;
     const Frame fr = interior_of(c);
     const int cz = std::min(frame_cz(c), c->p.nz);
-    if (c->ftiles && cz == c->fcz && fr.x0 == c->ftile_rect.x0 && fr.x1 == c->ftile_rect.x1 &&
+    const int rows = c->frame_rows;
+    if (c->ftiles && cz == c->fcz && rows == c->frows && fr.x0 == c->ftile_rect.x0 &&
+        fr.x1 == c->ftile_rect.x1 &&
         fr.y0 == c->ftile_rect.y0 && fr.y1 == c->ftile_rect.y1)
         return;
     const Problem& p = c->p;
     std::vector<int4> t;
     for (int ch = 0; ch * cz < p.nz; ++ch)
-        for (int y0 = 0; y0 < p.ny; y0 += BND_ROWS)
+        for (int y0 = 0; y0 < p.ny; y0 += rows)
             for (int x0 = 0; x0 < p.nx; x0 += 64) {
                 const bool inside = x0 >= fr.x0 && x0 + 64 <= fr.x1 && y0 >= fr.y0 &&
-                                    y0 + BND_ROWS <= fr.y1;
+                                    y0 + rows <= fr.y1;
                 if (!inside) t.push_back(make_int4(0, x0, y0, ch));
             }
     check(hipStreamSynchronize(c->stream), "sync");   // the old list may be in use
@@ -244,10 +248,11 @@ inline void ensure_frame_tiles(fdtd_ctx* c) {
           "copy frame tiles");
     c->nftiles = (int)t.size();
     c->fcz = cz;
+    c->frows = rows;
     c->ftile_rect = fr;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
-    c->fblocks = std::max(1, std::min((c->nftiles + 3) / 4, cus * fused_bnd_blocks_per_cu()));
+    c->fblocks = std::max(1, std::min((c->nftiles + 3) / 4, cus * fused_bnd_blocks_per_cu(rows, false)));
 }
 
 inline void ensure_partials(fdtd_ctx* c) {
@@ -272,9 +277,9 @@ inline hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, 
     }
     if (frame_fused(c)) {
         if (c->timer) c->timer->mark("frame_fused");
-        hipError_t e = launch_fused_bnd(q, nullptr, c->ftiles, c->nftiles, c->fcz, c->fblocks,
-                                        nullptr, n, parity, 1, fr, epart ? epart + off : nullptr,
-                                        c->stream);
+        hipError_t e = launch_fused_bnd(q, nullptr, c->ftiles, c->nftiles, c->frows, c->fcz,
+                                        c->fblocks, nullptr, n, parity, 1, fr,
+                                        epart ? epart + off : nullptr, c->stream);
         if (c->timer) c->timer->mark(nullptr);
         return e;
     }

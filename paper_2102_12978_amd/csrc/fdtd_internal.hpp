@@ -145,13 +145,14 @@ hipError_t launch_batch_advance(long long* nctr, int by, hipStream_t s);
 int batch_blocks_per_cu(int cols);   // resident workgroups per CU of both batch kernels
 
 // Fused step over boundary tiles (kernels_fused_bnd.hip): tiles (instance,
-// x0, y0, z chunk of cz planes) of probs[instance], or of `single` when probs
-// is null; cells inside excl are not stored. Step index *nctr + n_off (nctr
-// may be null). epart: one partial per tile, or null.
+// x0, y0, z chunk of cz planes) of 64 x cells by rows (2 or 4) rows, of
+// probs[instance], or of `single` when probs is null; cells inside excl are
+// not stored. Step index *nctr + n_off (nctr may be null). epart: one
+// partial per tile, or null.
 hipError_t launch_fused_bnd(const Problem& single, const Problem* probs, const int4* tiles,
-                            int ntiles, int cz, int blocks, const long long* nctr, long long n_off,
-                            int par, int diag, const Frame& excl, double* epart, hipStream_t s);
-int fused_bnd_blocks_per_cu();
-constexpr int BND_ROWS = 4;          // rows per boundary tile
+                            int ntiles, int rows, int cz, int blocks, const long long* nctr,
+                            long long n_off, int par, int diag, const Frame& excl, double* epart,
+                            hipStream_t s);
+int fused_bnd_blocks_per_cu(int rows, bool multi);
 
 }  // namespace bfdtd

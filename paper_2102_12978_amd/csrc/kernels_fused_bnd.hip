@@ -75,7 +75,7 @@ __device__ __forceinline__ void bhalo_slot(int q, int x0, int* c, int* r, int* x
 // kernel argument or global memory), so no generic pointer reaches the
 // per-cell code.
 template <int TY, bool MULTI>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(TY == 2 ? 3 : 2)))
 fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* __restrict__ tiles,
                  int ntiles, int cz, const long long* __restrict__ nctr, long long n_off, int par,
                  int diag, Frame excl, double* epart) {
@@ -372,27 +372,42 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
 }  // namespace
 
 hipError_t launch_fused_bnd(const Problem& single, const Problem* probs, const int4* tiles,
-                            int ntiles, int cz, int blocks, const long long* nctr, long long n_off,
-                            int par, int diag, const Frame& excl, double* epart, hipStream_t s) {
+                            int ntiles, int rows, int cz, int blocks, const long long* nctr,
+                            long long n_off, int par, int diag, const Frame& excl, double* epart,
+                            hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    if (probs)
-        hipLaunchKernelGGL((fused_bnd_kernel<4, true>), dim3(blocks), dim3(64 * WAVES), 0, s,
-                           single, probs, tiles, ntiles, cz, nctr, n_off, par, diag, excl, epart);
+    if (rows != 2 && rows != 4) return hipErrorInvalidValue;
+    const dim3 g(blocks), b(64 * WAVES);
+    if (probs && rows == 4)
+        hipLaunchKernelGGL((fused_bnd_kernel<4, true>), g, b, 0, s, single, probs, tiles, ntiles,
+                           cz, nctr, n_off, par, diag, excl, epart);
+    else if (probs)
+        hipLaunchKernelGGL((fused_bnd_kernel<2, true>), g, b, 0, s, single, probs, tiles, ntiles,
+                           cz, nctr, n_off, par, diag, excl, epart);
+    else if (rows == 4)
+        hipLaunchKernelGGL((fused_bnd_kernel<4, false>), g, b, 0, s, single, probs, tiles, ntiles,
+                           cz, nctr, n_off, par, diag, excl, epart);
     else
-        hipLaunchKernelGGL((fused_bnd_kernel<4, false>), dim3(blocks), dim3(64 * WAVES), 0, s,
-                           single, probs, tiles, ntiles, cz, nctr, n_off, par, diag, excl, epart);
+        hipLaunchKernelGGL((fused_bnd_kernel<2, false>), g, b, 0, s, single, probs, tiles, ntiles,
+                           cz, nctr, n_off, par, diag, excl, epart);
     return hipGetLastError();
 }
 
-int fused_bnd_blocks_per_cu() {
-    int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, fused_bnd_kernel<4, true>, 64 * WAVES,
-                                                     0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<4, false>, 64 * WAVES,
-                                                     0) != hipSuccess)
-        return 1;
-    const int m = a < b ? a : b;
-    return m > 0 ? m : 1;
+int fused_bnd_blocks_per_cu(int rows, bool multi) {
+    int b = 0;
+    hipError_t e;
+    if (rows == 4)
+        e = multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<4, true>,
+                                                                 64 * WAVES, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<4, false>,
+                                                                 64 * WAVES, 0);
+    else
+        e = multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<2, true>,
+                                                                 64 * WAVES, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fused_bnd_kernel<2, false>,
+                                                                 64 * WAVES, 0);
+    if (e != hipSuccess) return 1;
+    return b > 0 ? b : 1;
 }
 
 }  // namespace bfdtd

@@ -192,8 +192,8 @@ class Solver:
     def set_tile(self, rows, zchunk=0):
         self._c(self._lib.fdtd_set_tile(self._ctx, rows, zchunk))
 
-    def set_frame(self, kind, xalign=32):
-        self._c(self._lib.fdtd_set_frame(self._ctx, int(kind), int(xalign)))
+    def set_frame(self, kind, xalign=32, rows=2):
+        self._c(self._lib.fdtd_set_frame(self._ctx, int(kind), int(xalign), int(rows)))
 
     def profile(self, on=True):
         self._c(self._lib.fdtd_profile_enable(self._ctx, 1 if on else 0))

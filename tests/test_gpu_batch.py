@@ -91,12 +91,14 @@ def test_autotune_leaves_state_alone():
     b.close()
 
 
-@pytest.mark.parametrize("kernel,cols,zchunk", [(L.KERNEL_SPLIT, 64, 5), (L.KERNEL_SPLIT, 128, 0),
-                                                (L.KERNEL_FUSED, 64, 5), (L.KERNEL_FUSED, 64, 0)])
-def test_tile_shapes_agree(kernel, cols, zchunk):
+@pytest.mark.parametrize("kernel,cols,zchunk,rows", [(L.KERNEL_SPLIT, 64, 5, 2),
+                                                     (L.KERNEL_SPLIT, 128, 0, 2),
+                                                     (L.KERNEL_FUSED, 64, 5, 2),
+                                                     (L.KERNEL_FUSED, 64, 0, 4)])
+def test_tile_shapes_agree(kernel, cols, zchunk, rows):
     ws = W.batch_small()
     a = Batch(ws)
-    a.set_kernel(kernel)
+    a.set_kernel(kernel, rows)
     a.set_tile(cols, zchunk)
     a.step(24)
     for q, w in enumerate(ws):

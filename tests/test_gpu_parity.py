@@ -242,17 +242,18 @@ def test_source_linearity_on_gpu():
     b.close()
 
 
-@pytest.mark.parametrize("xalign,rows,zchunk", [(32, 4, 0), (64, 4, 7), (64, 8, 9), (32, 8, 16)])
-def test_fused_frame(xalign, rows, zchunk):
+@pytest.mark.parametrize("xalign,rows,zchunk,frows", [(32, 4, 0, 2), (64, 4, 7, 4), (64, 8, 9, 2),
+                                                      (32, 8, 16, 4)])
+def test_fused_frame(xalign, rows, zchunk, frows):
     """The frame stepped by the fused boundary-tile kernel (one launch over
     the 64 x 4 tiles that hold frame cells): 300×150, antenna across interior
     and frame, z chunks that do not divide nz; against the oracle (fields and
     CPML memories) and against the split-kernel frame."""
     w = W.parity_mid()
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=rows, zchunk=zchunk)
-    s.set_frame(L.FRAME_FUSED, xalign)
+    s.set_frame(L.FRAME_FUSED, xalign, frows)
     inf = s.info()
-    assert inf.frame == L.FRAME_FUSED and inf.xalign == xalign
+    assert inf.frame == L.FRAME_FUSED and inf.xalign == xalign and inf.frame_rows == frows
     s.step(w.steps)
     g, st = GC.oracle_run(w, w.steps)
     _compare(s, st, g)
@@ -271,7 +272,7 @@ def test_fused_frame_small_grids(maker):
     whole grid or a ragged ring (PEC walls, CPML corners, lanes past nx)."""
     w = maker()
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
-    s.set_frame(L.FRAME_FUSED, 64)
+    s.set_frame(L.FRAME_FUSED, 64, 4 if maker is W.config0 else 2)
     s.step(w.steps)
     g, st = GC.oracle_run(w, w.steps)
     _compare(s, st, g)
