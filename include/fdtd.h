@@ -420,7 +420,8 @@ int fdtd_batch_step(fdtd_batch *b, int64_t nsteps);
 int fdtd_batch_set_kernel(fdtd_batch *b, int32_t kernel, int32_t rows);
 
 /* Work-item shape: cols in {64, 128, 256} (split kernel only), zchunk >= 0
- * (z planes per work item, 0 = whole z). */
+ * (z planes per work item, 0 = whole z; for the split kernel 1 launches one
+ * workgroup per column block and plane instead of the persistent grid). */
 int fdtd_batch_set_tile(fdtd_batch *b, int32_t cols, int32_t zchunk);
 
 /* Steps recorded per graph: an even number in [2, 1000], or 0 to launch

@@ -21,7 +21,8 @@ struct fdtd_batch {
     long long* nctr = nullptr;         // device step counter read by the kernels
     int4* work = nullptr;
     int nwork = 0;
-    int cols = 256, zchunk = 0, blocks = 0;
+    int cols = 256, zchunk = 1, blocks = 0;
+    int planes = 0;                    // split kernels with zchunk 1: one block per plane
     int kernel = FDTD_KERNEL_SPLIT;    // split E/H passes, or fused boundary tiles
     int bnd_rows = 2;                  // rows per fused boundary tile (2 or 4)
     int graph_steps = 20;              // even, so a replay leaves the parity unchanged
@@ -88,10 +89,18 @@ void build_work(fdtd_batch* b) {
             continue;
         }
         const int ncol = p.pitch * p.ny;   // columns over the padded pitch (x >= nx idle)
+        if (b->zchunk == 1) {              // plane grid: the kernels take k from the grid
+            for (int c0 = 0; c0 < ncol; c0 += b->cols) w.push_back(make_int4(q, c0, 0, 1));
+            continue;
+        }
         const int zc = b->zchunk > 0 ? std::min(b->zchunk, p.nz) : p.nz;
         for (int c0 = 0; c0 < ncol; c0 += b->cols)
             for (int k0 = 0; k0 < p.nz; k0 += zc) w.push_back(make_int4(q, c0, k0, std::min(k0 + zc, p.nz)));
     }
+    b->planes = 0;
+    if (b->kernel != FDTD_KERNEL_FUSED && b->zchunk == 1)
+        for (const auto& c : b->inst) b->planes = std::max(b->planes, c->p.nz);
+    need(b->planes <= 65535, "z extent too large for a per-plane grid");
     need(w.size() < (size_t)1 << 30, "too many work items");
     check(hipStreamSynchronize(b->stream), "sync");
     drop_graphs(b);
@@ -139,10 +148,11 @@ hipError_t launch_pair(const fdtd_batch* b, hipStream_t s, int off, int par, int
         return launch_fused_bnd(b->host_probs[0], b->probs, b->work, b->nwork, b->bnd_rows,
                                 fused_cz(b), b->blocks, b->nctr, off, par, diag,
                                 Frame{0, 0, 0, 0}, nullptr, s);
-    hipError_t e = launch_batch_e(b->probs, b->work, b->nwork, b->cols, b->blocks, b->nctr, off,
-                                  par, diag, s);
+    hipError_t e = launch_batch_e(b->probs, b->work, b->nwork, b->cols, b->blocks, b->planes,
+                                  b->nctr, off, par, diag, s);
     if (e != hipSuccess) return e;
-    return launch_batch_h(b->probs, b->work, b->nwork, b->cols, b->blocks, b->nctr, off, par, s);
+    return launch_batch_h(b->probs, b->work, b->nwork, b->cols, b->blocks, b->planes, b->nctr,
+                          off, par, s);
 }
 
 // Record graph_steps steps starting at parity par, then the counter advance.

@@ -133,14 +133,17 @@ hipError_t launch_split_frame(const Problem& p, long long n, int parity, const F
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 
 // Batched kernels over many instances (kernels_batch.hip). A work item is
-// (instance, first flattened column, k begin, k end); the E and H kernels
-// loop over the items with a persistent grid of `blocks` workgroups of
-// `cols` threads. The step index is *nctr + off (a device counter so that a
-// captured graph can be replayed); par is the parity read.
+// (instance, first flattened column, k begin, k end); with planes == 0 the E
+// and H kernels loop over the items with a persistent grid of `blocks`
+// workgroups of `cols` threads; with planes > 0 they launch one workgroup per
+// (item, plane < planes) and ignore the items' k range. The step index is
+// *nctr + off (a device counter so that a captured graph can be replayed);
+// par is the parity read.
 hipError_t launch_batch_e(const Problem* probs, const int4* work, int nwork, int cols, int blocks,
-                          const long long* nctr, int off, int par, int diag, hipStream_t s);
+                          int planes, const long long* nctr, int off, int par, int diag,
+                          hipStream_t s);
 hipError_t launch_batch_h(const Problem* probs, const int4* work, int nwork, int cols, int blocks,
-                          const long long* nctr, int off, int par, hipStream_t s);
+                          int planes, const long long* nctr, int off, int par, hipStream_t s);
 hipError_t launch_batch_advance(long long* nctr, int by, hipStream_t s);
 int batch_blocks_per_cu(int cols);   // resident workgroups per CU of both batch kernels
 

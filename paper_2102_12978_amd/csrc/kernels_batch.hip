@@ -54,6 +54,38 @@ batch_h_kernel(const Problem* __restrict__ probs, const int4* __restrict__ work,
     }
 }
 
+// One workgroup per (column block, plane): block x is the work item (its
+// k range unused), block y the plane; planes past an instance's nz exit.
+// No loop, so every cell's loads are in flight at once across the grid.
+template <int par>
+__global__ void __launch_bounds__(MAX_COLS)
+batch_e_plane_kernel(const Problem* __restrict__ probs, const int4* __restrict__ work,
+                     const long long* __restrict__ nctr, int off, int diag) {
+    const long long n = *nctr + off;
+    const int4 wk = work[blockIdx.x];
+    const Problem p = probs[wk.x];
+    const int k = blockIdx.y;
+    const int col = wk.y + (int)threadIdx.x;
+    const int i = col % p.pitch, j = col / p.pitch;
+    if (k >= p.nz || i >= p.nx || j >= p.ny) return;
+    const int mask = (diag && n >= p.win_begin) ? p.diag_mask : 0;
+    (void)e_point(p, n, par, i, j, k, mask);
+}
+
+template <int par>
+__global__ void __launch_bounds__(MAX_COLS)
+batch_h_plane_kernel(const Problem* __restrict__ probs, const int4* __restrict__ work,
+                     const long long* __restrict__ nctr, int off) {
+    const long long n = *nctr + off;
+    const int4 wk = work[blockIdx.x];
+    const Problem p = probs[wk.x];
+    const int k = blockIdx.y;
+    const int col = wk.y + (int)threadIdx.x;
+    const int i = col % p.pitch, j = col / p.pitch;
+    if (k >= p.nz || i >= p.nx || j >= p.ny) return;
+    (void)h_point(p, n, par, i, j, k);
+}
+
 __global__ void batch_advance_kernel(long long* nctr, int by) {
     if (threadIdx.x == 0 && blockIdx.x == 0) nctr[0] += by;
 }
@@ -61,8 +93,19 @@ __global__ void batch_advance_kernel(long long* nctr, int by) {
 }  // namespace
 
 hipError_t launch_batch_e(const Problem* probs, const int4* work, int nwork, int cols, int blocks,
-                          const long long* nctr, int off, int par, int diag, hipStream_t s) {
+                          int planes, const long long* nctr, int off, int par, int diag,
+                          hipStream_t s) {
     if (cols < 1 || cols > MAX_COLS || blocks < 1) return hipErrorInvalidValue;
+    if (planes > 0) {
+        const dim3 g((unsigned)nwork, (unsigned)planes);
+        if (par)
+            hipLaunchKernelGGL(batch_e_plane_kernel<1>, g, dim3(cols), 0, s, probs, work, nctr,
+                               off, diag);
+        else
+            hipLaunchKernelGGL(batch_e_plane_kernel<0>, g, dim3(cols), 0, s, probs, work, nctr,
+                               off, diag);
+        return hipGetLastError();
+    }
     if (par)
         hipLaunchKernelGGL(batch_e_kernel<1>, dim3(blocks), dim3(cols), 0, s, probs, work, nwork,
                            nctr, off, diag);
@@ -73,8 +116,18 @@ hipError_t launch_batch_e(const Problem* probs, const int4* work, int nwork, int
 }
 
 hipError_t launch_batch_h(const Problem* probs, const int4* work, int nwork, int cols, int blocks,
-                          const long long* nctr, int off, int par, hipStream_t s) {
+                          int planes, const long long* nctr, int off, int par, hipStream_t s) {
     if (cols < 1 || cols > MAX_COLS || blocks < 1) return hipErrorInvalidValue;
+    if (planes > 0) {
+        const dim3 g((unsigned)nwork, (unsigned)planes);
+        if (par)
+            hipLaunchKernelGGL(batch_h_plane_kernel<1>, g, dim3(cols), 0, s, probs, work, nctr,
+                               off);
+        else
+            hipLaunchKernelGGL(batch_h_plane_kernel<0>, g, dim3(cols), 0, s, probs, work, nctr,
+                               off);
+        return hipGetLastError();
+    }
     if (par)
         hipLaunchKernelGGL(batch_h_kernel<1>, dim3(blocks), dim3(cols), 0, s, probs, work, nwork,
                            nctr, off);

@@ -93,6 +93,7 @@ def test_autotune_leaves_state_alone():
 
 @pytest.mark.parametrize("kernel,cols,zchunk,rows", [(L.KERNEL_SPLIT, 64, 5, 2),
                                                      (L.KERNEL_SPLIT, 128, 0, 2),
+                                                     (L.KERNEL_SPLIT, 256, 1, 2),
                                                      (L.KERNEL_FUSED, 64, 5, 2),
                                                      (L.KERNEL_FUSED, 64, 0, 4)])
 def test_tile_shapes_agree(kernel, cols, zchunk, rows):
