@@ -70,3 +70,30 @@ def test_null_arguments_are_rejected():
     assert lib.fdtd_destroy(None) == L.OK
     assert lib.fdtd_step(None, 1) == L.EINVAL
     assert lib.fdtd_get_info(None, None) == L.EINVAL
+
+
+def test_stream_probe_validates_before_touching_the_gpu():
+    lib = L.load()
+    ms, gbs = ctypes.c_double(), ctypes.c_double()
+    bad = [(3, 1 << 20, 5), (-1, 1 << 20, 5), (0, 0, 5), (0, (1 << 20) + 4, 5), (0, 1 << 20, 0),
+           (0, 1 << 20, 1001)]
+    for kind, nbytes, reps in bad:
+        assert lib.fdtd_stream_probe(kind, nbytes, reps, None, ctypes.byref(ms),
+                                     ctypes.byref(gbs)) == L.EINVAL
+    assert lib.fdtd_stream_probe(0, 1 << 20, 5, None, None, None) == L.EINVAL
+
+
+def test_frame_and_batch_setters_reject_null_handles():
+    lib = L.load()
+    assert lib.fdtd_set_frame(None, L.FRAME_FUSED, 32, 2) == L.EINVAL
+    assert lib.fdtd_batch_set_kernel(None, L.KERNEL_FUSED, 2) == L.EINVAL
+    assert lib.fdtd_batch_set_tile(None, 256, 1) == L.EINVAL
+
+
+def test_polarisation_constants_match_the_header():
+    text = open(L.HEADER).read()
+    for name, value in (("FDTD_POL_X_TE", L.POL_X_TE), ("FDTD_POL_Y_TE", L.POL_Y_TE),
+                        ("FDTD_POL_Z_TE", L.POL_Z_TE), ("FDTD_POL_X_TM", L.POL_X_TM),
+                        ("FDTD_POL_Y_TM", L.POL_Y_TM), ("FDTD_POL_Z_TM", L.POL_Z_TM),
+                        ("FDTD_FRAME_SPLIT", L.FRAME_SPLIT), ("FDTD_FRAME_FUSED", L.FRAME_FUSED)):
+        assert f"#define {name} {value}" in text, name
