@@ -122,8 +122,8 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
         p.sy = (float)(grid->courant / c->ry);
         p.sz = (float)(grid->courant / c->rz);
         p.fstride = (long long)field_elems(p);
-        need(field_elems(p) * sizeof(float) < (1ull << 32),
-             "one field component must stay below 4 GiB (32-bit offsets)");
+        need((size_t)p.ny * p.pitch * sizeof(float) < (1ull << 31),
+             "one z plane of a field component must stay below 2 GiB (32-bit offsets)");
         if (p.npml > 0) {
             p.psx = (long long)psix_elems(p);
             p.psy = (long long)psiy_elems(p);

@@ -24,7 +24,8 @@
 //   * z: E_new(k+1) is formed from H_old(k+1) and H_old(k), then H_new(k)
 //     from E_new(k) and E_new(k+1); the z index wraps (periodic axis).
 // Addresses are a uniform component base (scalar registers) plus a 32-bit
-// per-lane byte offset. The new fields are written with non-temporal stores:
+// per-lane byte offset; components of 4 GiB or more use a 64-bit plane base
+// instead, with the 32-bit offset inside the plane. The new fields are written with non-temporal stores:
 // nothing reads them again in this launch, and keeping them out of the
 // caches leaves room for the halo rows that neighbouring tiles re-read.
 // Hardware block b runs on XCD b % 8; the block index is remapped so each
@@ -55,12 +56,16 @@ struct Interior {
     int x_org, y_org, nseg, nrow, ncz, cz;
 };
 
-template <int TY>
+// BIG: a field component spans 4 GiB or more, so plane bases are 64-bit
+// (scalar) and only the in-plane offset is 32-bit; otherwise the whole
+// offset is one 32-bit value.
+template <int TY, bool BIG>
 struct Tile {
     const Problem& p;
     int x, j0, lane;
     unsigned ro[TY + 2];   // byte offset of (row j0 + r, x) in a plane, r = -1..TY
-    unsigned pstride;      // bytes per plane
+    size_t plane;          // floats per plane
+    unsigned pstride;      // bytes per plane (when !BIG)
     const float* fo[6];    // component bases, old parity
     float* fw[6];          // component bases, new parity
 
@@ -69,7 +74,8 @@ struct Tile {
         x = x0 + lane;
 #pragma unroll
         for (int r = -1; r <= TY; ++r) ro[r + 1] = 4u * (unsigned)((j0 + r) * p.pitch + x);
-        pstride = 4u * (unsigned)(p.ny * p.pitch);
+        plane = (size_t)p.ny * p.pitch;
+        pstride = 4u * (unsigned)plane;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
             fo[c] = p.fbase[par] + c * p.fstride;
@@ -77,10 +83,14 @@ struct Tile {
         }
     }
     __device__ float ld(int c, int kk, int r) const {
+        if (BIG) return ldo(fo[c] + (size_t)kk * plane, ro[r + 1]);
         return ldo(fo[c], (unsigned)kk * pstride + ro[r + 1]);
     }
     __device__ void st(int c, int kk, int r, float v) const {
-        sto(fw[c], (unsigned)kk * pstride + ro[r + 1], v);
+        if (BIG)
+            sto(fw[c] + (size_t)kk * plane, ro[r + 1], v);
+        else
+            sto(fw[c], (unsigned)kk * pstride + ro[r + 1], v);
     }
 };
 
@@ -196,7 +206,7 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, long long n, int 
     }
 }
 
-template <int TY>
+template <int TY, bool BIG>
 __global__ void __launch_bounds__(64 * WAVES)
 __attribute__((amdgpu_waves_per_eu(TY == 4 ? 3 : 2)))
 fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_padded,
@@ -216,7 +226,7 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
         return;
     }
     const int j0 = I.y_org + sy * TY;
-    const Tile<TY> T(p, par, I.x_org + SEG * seg, j0);
+    const Tile<TY, BIG> T(p, par, I.x_org + SEG * seg, j0);
     const int lane = T.lane;
     const int nz = p.nz, nx = p.nx, ny = p.ny;
     const bool right = lane == 63;
@@ -413,8 +423,12 @@ hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, in
     if (nb <= 0) return hipSuccess;
     const int nbp = (nb + 7) / 8 * 8;
     if (timer) timer->mark("fused_interior");
-    hipLaunchKernelGGL(fused_interior_kernel<TY>, dim3(nbp), dim3(64 * WAVES), 0, s, p, n,
-                       parity, I, nbp, epart);
+    if ((size_t)p.fstride * sizeof(float) >= ((size_t)1 << 32))
+        hipLaunchKernelGGL((fused_interior_kernel<TY, true>), dim3(nbp), dim3(64 * WAVES), 0, s,
+                           p, n, parity, I, nbp, epart);
+    else
+        hipLaunchKernelGGL((fused_interior_kernel<TY, false>), dim3(nbp), dim3(64 * WAVES), 0, s,
+                           p, n, parity, I, nbp, epart);
     return hipGetLastError();
 }
 

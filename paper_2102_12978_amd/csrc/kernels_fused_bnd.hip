@@ -92,7 +92,7 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
         const int x = x0 + lane;
         const bool xin = x < nx;
         const int mask = (diag && n >= p.win_begin) ? p.diag_mask : 0;
-        const unsigned pstride = 4u * (unsigned)(ny * p.pitch);
+        const size_t plane = (size_t)ny * p.pitch;   // floats per plane
         gptr<const float> fo[6];
         gptr<float> fw[6];
 #pragma unroll
@@ -110,7 +110,7 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             ro[r + 1] = 4u * (unsigned)(min(max(y, 0), ny - 1) * p.pitch + x);
         }
         auto ld = [&](int c, int kk, int r) -> float {
-            const float v = ldb(fo[c], (unsigned)kk * pstride + ro[r + 1]);
+            const float v = ldb(fo[c] + (size_t)kk * plane, ro[r + 1]);
             return rv[r + 1] ? v : 0.f;
         };
         auto owned = [&](int r) -> bool {
@@ -234,10 +234,10 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
                 if (!owned(r)) continue;
-                const unsigned off = (unsigned)kk * pstride + ro[r + 1];
-                stb(fw[EX], off, ex[r]);
-                stb(fw[EY], off, ey[r]);
-                stb(fw[EZ], off, ez[r]);
+                const size_t pk = (size_t)kk * plane;
+                stb(fw[EX] + pk, ro[r + 1], ex[r]);
+                stb(fw[EY] + pk, ro[r + 1], ey[r]);
+                stb(fw[EZ] + pk, ro[r + 1], ez[r]);
                 if (epart) en += (double)ex[r] * ex[r] + (double)ey[r] * ey[r] + (double)ez[r] * ez[r];
                 if (kk == p.plane) {
                     const size_t pl = (size_t)(j0 + r) * nx + x, ps = (size_t)nx * ny;
@@ -342,10 +342,10 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
                 e.ez_jp = ecz[r + 1];
                 float vx = hcx[r], vy = hcy[r], vz = hcz[r];
                 h_cell<true>(p, par, x, j0 + r, k, e, vx, vy, vz, slot[r], qt0, qt1);
-                const unsigned off = (unsigned)k * pstride + ro[r + 1];
-                stb(fw[HX], off, vx);
-                stb(fw[HY], off, vy);
-                stb(fw[HZ], off, vz);
+                const size_t pk = (size_t)k * plane;
+                stb(fw[HX] + pk, ro[r + 1], vx);
+                stb(fw[HY] + pk, ro[r + 1], vy);
+                stb(fw[HZ] + pk, ro[r + 1], vz);
                 if (epart) en += (double)hcx[r] * vx + (double)hcy[r] * vy + (double)hcz[r] * vz;
             }
             if (k + 1 < ke) store_e(kn, ex, ey, ez);

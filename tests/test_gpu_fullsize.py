@@ -65,3 +65,53 @@ def test_large_grid_sampled_columns():
     print(f"  {len(COLUMNS)} columns x {g.nz} planes x 6 components: rel-L2 {rel:.2e}, "
           f"max |diff| {worst:.2e}", flush=True)
     assert rel <= 1e-5 and worst <= 1e-5
+
+
+def test_component_beyond_4_gib():
+    """A grid whose field components exceed 4 GiB (2048×1024×536, 1.12 G
+    cells, 54 GB of fields): planes past 512 lie beyond 32-bit byte offsets,
+    so the fused kernel takes 64-bit plane bases. Random fields in windows
+    around sampled columns (zero elsewhere), antenna on, three steps; whole
+    columns (every plane) against the windowed FP64 oracle."""
+    w = W.Workload("big_2048x1024x536_theta20_m1", 2048, 1024, 540, 24.0, 20.0, 1, 400.0, 2.0,
+                   16, 3)
+    steps = 3
+    g = cases.oracle_grid(w)
+    assert g.nz * g.ny * 2048 * 4 > (1 << 32)
+    cols = [(1024 - 399, 512), (1024 + 399, 512), (1024, 512 + 399), (700, 300), (64, 700),
+            (2040, 1010), (1500, 16), (1024, 512)]
+    h = steps + 2
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=16)
+    ant = P.build_antenna(g, cases.oracle_injector(w))
+    rng = np.random.default_rng(11)
+    fields = {}
+    for q, c in enumerate(GC.COMPS):
+        a = np.zeros((g.nz, g.ny, g.nx), dtype=np.float32)
+        for (i, j) in cols:
+            a[:, j - h:j + h + 1, i - h:i + h + 1] = rng.uniform(
+                -1.0, 1.0, size=(g.nz, 2 * h + 1, 2 * h + 1))
+        if c in ("ex", "ey", "ez"):
+            a[:, Y.held_mask(g, c)] = 0.0
+        s.set_state(q, a)
+        fields[c] = a
+    print(f"  {w.name}: nz={g.nz}, component {g.nz * g.ny * g.nx * 4 / 2**30:.2f} GiB; "
+          f"state set, {steps} steps", flush=True)
+    s.step(steps)
+    num = den = worst = 0.0
+    got = {}
+    for q, c in enumerate(GC.COMPS):
+        full = s.get_state(q)
+        got[c] = {ij: full[:, ij[1], ij[0]].astype(np.float64) for ij in cols}
+        del full
+    s.close()
+    for (i, j) in cols:
+        ref = WN.column(g, ant, fields, {}, i, j, steps)
+        for c in GC.COMPS:
+            d = got[c][(i, j)] - ref[c]
+            num += float(np.sum(d * d))
+            den += float(np.sum(ref[c] ** 2))
+            worst = max(worst, float(np.abs(d).max()))
+    rel = (num / den) ** 0.5
+    print(f"  {len(cols)} columns x {g.nz} planes x 6 components: rel-L2 {rel:.2e}, "
+          f"max |diff| {worst:.2e}", flush=True)
+    assert rel <= 1e-5 and worst <= 1e-5
