@@ -26,23 +26,27 @@ __device__ __forceinline__ void block_energy(double v, double* out) {
     if (tid == 0) *out = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__device__ __forceinline__ bool frame_column(const Frame& fr, int nx, int ny, long long c, int* x,
+// Column c of the frame -> (x, y). A plane holds fewer than 2^31 cells (the
+// context checks it), so the index math is 32-bit: unsigned divisions are a
+// fraction of the cost of 64-bit ones.
+__device__ __forceinline__ bool frame_column(const Frame& fr, int nx, int ny, unsigned c, int* x,
                                              int* y) {
-    const long long nb = (long long)fr.y0 * nx;
-    const long long nt = (long long)(ny - fr.y1) * nx;
-    const long long nl = (long long)(fr.y1 - fr.y0) * fr.x0;
-    const long long nr = (long long)(fr.y1 - fr.y0) * (nx - fr.x1);
+    const unsigned unx = (unsigned)nx;
+    const unsigned nb = (unsigned)fr.y0 * unx;
+    const unsigned nt = (unsigned)(ny - fr.y1) * unx;
+    const unsigned nl = (unsigned)(fr.y1 - fr.y0) * (unsigned)fr.x0;
+    const unsigned nr = (unsigned)(fr.y1 - fr.y0) * (unsigned)(nx - fr.x1);
     if (c < nb) {
-        *y = (int)(c / nx);
-        *x = (int)(c % nx);
+        *y = (int)(c / unx);
+        *x = (int)(c % unx);
     } else if ((c -= nb) < nt) {
-        *y = fr.y1 + (int)(c / nx);
-        *x = (int)(c % nx);
+        *y = fr.y1 + (int)(c / unx);
+        *x = (int)(c % unx);
     } else if ((c -= nt) < nl) {
-        *y = fr.y0 + (int)(c / fr.x0);
-        *x = (int)(c % fr.x0);
+        *y = fr.y0 + (int)(c / (unsigned)fr.x0);
+        *x = (int)(c % (unsigned)fr.x0);
     } else if ((c -= nl) < nr) {
-        const int wdt = nx - fr.x1;
+        const unsigned wdt = (unsigned)(nx - fr.x1);
         *y = fr.y0 + (int)(c / wdt);
         *x = fr.x1 + (int)(c % wdt);
     } else {
@@ -55,8 +59,8 @@ __global__ void __launch_bounds__(BT)
 split_e_kernel(Problem p, long long n, int par, Frame fr, long long ncols, double* epart) {
     int i = 0, j = 0;
     const int k = blockIdx.y;
-    const long long col = (long long)blockIdx.x * BT + threadIdx.x;
-    const bool inside = col < ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
+    const unsigned col = blockIdx.x * BT + threadIdx.x;
+    const bool inside = col < (unsigned long long)ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
     const double e2 = inside ? e_point(p, n, par, i, j, k, p.diag_mask) : 0.0;
     if (epart) block_energy(e2, epart + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
@@ -65,8 +69,8 @@ __global__ void __launch_bounds__(BT)
 split_h_kernel(Problem p, long long n, int par, Frame fr, long long ncols, double* epart) {
     int i = 0, j = 0;
     const int k = blockIdx.y;
-    const long long col = (long long)blockIdx.x * BT + threadIdx.x;
-    const bool inside = col < ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
+    const unsigned col = blockIdx.x * BT + threadIdx.x;
+    const bool inside = col < (unsigned long long)ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
     const double hh = inside ? h_point(p, n, par, i, j, k) : 0.0;
     if (epart) block_energy(hh, epart + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
