@@ -236,7 +236,9 @@ int fdtd_analytic_ey2(fdtd_ctx *ctx, float *host_out, int64_t n);
 /* Select the fused kernel's tile shape explicitly: y rows per wavefront in
  * {4, 8} (a wavefront covers 64 x cells and marches along z); z chunk in
  * planes per wavefront, 0 = the whole z extent. Returns FDTD_EINVAL
- * otherwise. */
+ * otherwise. A new context starts with 4 rows and the z
+ * chunk that gives the interior kernel about 32 workgroups per compute unit
+ * (at least 4 planes; the whole z when that already suffices). */
 int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
 
 /* How the fused kernel's frame (the CPML slabs, walls and the cells the

@@ -145,6 +145,9 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
         c->fl = dalloc<double>(c, 3 * (size_t)p.nx * p.ny);
         p.fl = c->fl;
         c->energy_dev = dalloc<double>(c, 1);
+        int cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+        c->zchunk = fused_default_zchunk(p, c->rows, c->xalign, cus);
         ensure_partials(c);
         check(hipStreamSynchronize(c->stream), "sync");
     });

@@ -121,6 +121,9 @@ struct Frame {
 // xalign: the interior starts on a multiple of 32 or 64 cells in x.
 Frame fused_interior_rect(const Problem& p, int rows, int xalign);
 int fused_interior_tiles(const Problem& p, int rows, int zchunk, int xalign);
+// z chunk giving the interior kernel about 32 workgroups per CU (at least 4
+// planes per chunk; 0: the whole z already gives that many)
+int fused_default_zchunk(const Problem& p, int rows, int xalign, int cus);
 hipError_t launch_fused_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
                                  int xalign, double* epart, hipStream_t s, LaunchTimer* timer);
 

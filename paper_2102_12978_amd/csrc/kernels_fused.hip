@@ -33,6 +33,8 @@
 // neighbouring tiles stay in one L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels_common.hpp"
 
 namespace bfdtd {
@@ -438,6 +440,17 @@ Frame fused_interior_rect(const Problem& p, int rows, int xalign) {
     const Interior I = interior(p, rows, 0, xalign);
     if (I.nseg <= 0) return Frame{0, 0, 0, 0};
     return Frame{I.x_org, I.x_org + SEG * I.nseg, I.y_org, I.y_org + rows * I.nrow};
+}
+
+int fused_default_zchunk(const Problem& p, int rows, int xalign, int cus) {
+    const Interior I = interior(p, rows, 0, xalign);
+    if (I.nseg <= 0) return 0;
+    const long long base = group_count(I);          // workgroups with the whole z
+    const long long target = 32LL * (cus > 0 ? cus : 256);
+    if (base >= target) return 0;
+    const long long chunks = (target + base - 1) / base;
+    const int cz = (int)std::max<long long>(4, (p.nz + chunks - 1) / chunks);
+    return cz >= p.nz ? 0 : cz;
 }
 
 int fused_interior_tiles(const Problem& p, int rows, int zchunk, int xalign) {
