@@ -198,28 +198,38 @@ __global__ void __launch_bounds__(BT) adj_inject_kernel(Problem p, const float* 
 
 // G_c(slot) += T(t) Σ_k λ_c(k, j, i) e^{iβ z_c(k)} for one half step: three
 // components (first = EX or HX) of every antenna column, in double.
+// One wavefront per (antenna column, component): lane l sums the planes
+// k = l, l + 64, ... of that column, then the wavefront adds the lanes in a
+// fixed butterfly order, so the result does not depend on scheduling. All
+// planes of a column are in flight at once (a thread per column would walk
+// them one after another).
 __global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, const int* slot_i,
                                                       const int* slot_j, int nslots, int first,
                                                       float2 t, double2* G) {
-    const int tid = blockIdx.x * BT + threadIdx.x;
-    if (tid >= nslots * 3) return;
-    const int s = tid / 3, c = first + tid % 3;
+    const int pair = blockIdx.x * (BT / 64) + (int)(threadIdx.x >> 6);
+    if (pair >= nslots * 3) return;                      // whole wavefront
+    const int lane = threadIdx.x & 63;
+    const int s = pair / 3, c = first + pair % 3;
     const int i = slot_i[s], j = slot_j[s];
     // integer-plane components: E_x, E_y, H_z; half-plane: E_z, H_x, H_y
     const int half = (c == EZ || c == HX || c == HY) ? 1 : 0;
     const float* f = p.fbase[0] + c * p.fstride + (size_t)j * p.pitch + i;
     const size_t plane = (size_t)p.ny * p.pitch;
     double re = 0.0, im = 0.0;
-    for (int k = 0; k < p.nz; ++k) {
+    for (int k = lane; k < p.nz; k += 64) {
         const double l = f[k * plane];
         const float2 z = p.zph[2 * k + half];
         re += l * z.x;
         im += l * z.y;
     }
-    double2 g = G[(size_t)s * 6 + c];
-    g.x += re * t.x - im * t.y;
-    g.y += re * t.y + im * t.x;
-    G[(size_t)s * 6 + c] = g;
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) {
+        double2 g = G[(size_t)s * 6 + c];
+        g.x += re * t.x - im * t.y;
+        g.y += re * t.y + im * t.x;
+        G[(size_t)s * 6 + c] = g;
+    }
 }
 
 }  // namespace
@@ -246,8 +256,9 @@ hipError_t launch_adjoint_inject(const Problem& lam, const float* g, const float
 hipError_t launch_adjoint_gacc(const Problem& lam, const int* slot_i, const int* slot_j,
                                int nslots, int first, float2 t, double2* G, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(adj_gacc_kernel, dim3((nslots * 3 + BT - 1) / BT), dim3(BT), 0, s, lam,
-                       slot_i, slot_j, nslots, first, t, G);
+    const int waves = BT / 64;
+    hipLaunchKernelGGL(adj_gacc_kernel, dim3((nslots * 3 + waves - 1) / waves), dim3(BT), 0, s,
+                       lam, slot_i, slot_j, nslots, first, t, G);
     return hipGetLastError();
 }
 
