@@ -205,7 +205,9 @@ int fdtd_set_diagnostics(fdtd_ctx *ctx, int32_t k_plane, int64_t window_begin_st
 int fdtd_step(fdtd_ctx *ctx, int64_t nsteps);
 
 /* Mean over the window of one plane quantity (FDTD_DIAG_EX2, _EY2 or _EZ2),
- * written to host_out[ny*nx] (x fastest). Synchronises. n = capacity. */
+ * written to host_out[ny*nx] (x fastest). Synchronises. n = capacity.
+ * Returns FDTD_EUNSTABLE (after writing host_out) if any sum is NaN or
+ * infinite. */
 int fdtd_fluence(fdtd_ctx *ctx, uint32_t quantity, float *host_out, int64_t n);
 
 /* Number of steps accumulated in the fluence sums. */

@@ -292,7 +292,12 @@ int fdtd_fluence(fdtd_ctx* c, uint32_t quantity, float* host_out, int64_t n) {
                              hipMemcpyDeviceToHost, c->stream), "copy fluence");
         check(hipStreamSynchronize(c->stream), "sync");
         const double inv = c->count > 0 ? 1.0 / (double)c->count : 0.0;
-        for (size_t q = 0; q < np; ++q) host_out[q] = (float)(h[q] * inv);
+        bool finite = true;
+        for (size_t q = 0; q < np; ++q) {
+            host_out[q] = (float)(h[q] * inv);
+            finite = finite && std::isfinite(h[q]);
+        }
+        need(finite, "fluence is not finite (the run has diverged)", FDTD_EUNSTABLE);
     });
 }
 

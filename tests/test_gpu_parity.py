@@ -186,6 +186,27 @@ def test_plane_diagnostics_and_energy():
     s.close()
 
 
+def test_divergence_reported():
+    """A non-finite value planted (from the host) on the diagnostic plane
+    makes both readbacks report FDTD_EUNSTABLE instead of returning NaN."""
+    w = W.parity_small()
+    g = cases.oracle_grid(w)
+    plane = g.nz // 2
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0)
+    s.set_diagnostics(plane, 0, L.DIAG_EY2 | L.DIAG_ENERGY)
+    s.step(2)
+    assert np.isfinite(s.fluence(L.DIAG_EY2)).all() and np.isfinite(s.energy())
+    ey = s.get_state(L.EY)
+    ey[plane, g.ny // 2, g.nx // 2] = np.nan
+    s.set_state(L.EY, ey)
+    s.step(1)
+    for read in (lambda: s.fluence(L.DIAG_EY2), s.energy):
+        with pytest.raises(L.FdtdError) as e:
+            read()
+        assert e.value.code == L.EUNSTABLE
+    s.close()
+
+
 def test_fused_equals_split():
     w = W.parity_mid()
     a = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
