@@ -149,7 +149,7 @@ typedef struct fdtd_info {
     int32_t frame;               /* FDTD_FRAME_* used around the interior     */
     int32_t xalign;              /* interior x origin multiple (32 or 64)     */
     int32_t frame_rows;          /* rows per fused frame tile (2 or 4)        */
-    int32_t reserved;
+    int32_t time_block;          /* steps per interior pass (1 or 2)          */
 } fdtd_info;
 
 /* Library version string (static storage). */
@@ -255,6 +255,20 @@ int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
 #define FDTD_FRAME_SPLIT 0
 #define FDTD_FRAME_FUSED 1
 int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
+
+/* Steps per pass over the interior (temporal blocking). steps = 1: every
+ * step runs the one-step kernels. steps = 2: pairs of steps run one
+ * two-step interior kernel (the Yee update of §4 applied twice in registers:
+ * each field is read and written once per pair, 24 B per cell-update) over
+ * tiles of 60 x cells by `rows` (2 or 4) rows marching through z chunks of
+ * zchunk planes (0 = the whole z), and the frame around it runs the split
+ * kernels in four passes through an intermediate copy of the fields, which
+ * this call allocates (six components; freed again by steps = 1). The result
+ * is bit-identical to one-step runs. Pairs fall back to single steps for
+ * the split kernel choice, the periodic test mode, grids too small for the
+ * two-step interior, and while the energy diagnostic is on; an odd last
+ * step runs alone. */
+int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchunk);
 
 /* Time candidate tile shapes and frame choices on the live problem (the state
  * is restored) and keep the fastest. *best_rows / *best_zchunk may be NULL. */

@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
                 ("tile_zchunk", ctypes.c_int32), ("step", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("interior_cells", ctypes.c_int64),
                 ("frame", ctypes.c_int32), ("xalign", ctypes.c_int32),
-                ("frame_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("frame_rows", ctypes.c_int32), ("time_block", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -104,6 +104,7 @@ _SIGS = {
     "fdtd_autotune": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_int32)]),
     "fdtd_set_frame": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "fdtd_set_time_block": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),

@@ -275,7 +275,16 @@ int fdtd_step(fdtd_ctx* c, int64_t nsteps) {
         need(nsteps >= 0, "nsteps must be >= 0");
         ensure_time_tables(c, c->step + nsteps);
         ensure_partials(c);
-        for (int64_t s = 0; s < nsteps; ++s) launch_one(c, c->step);
+        const bool pairs = two_step_rect(c).x1 > 0;
+        for (int64_t s = 0; s < nsteps;) {
+            if (pairs && nsteps - s >= 2) {
+                launch_pair(c, c->step);
+                s += 2;
+            } else {
+                launch_one(c, c->step);
+                s += 1;
+            }
+        }
     });
 }
 
@@ -427,9 +436,11 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->frame = c->frame;
     out->xalign = c->xalign;
     out->frame_rows = c->frame_rows;
+    out->time_block = c->time_block;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
-    const Frame fr = interior_of(c);
+    const Frame f2 = two_step_rect(c);
+    const Frame fr = f2.x1 > 0 ? f2 : interior_of(c);
     out->interior_cells = (long long)(fr.x1 - fr.x0) * (fr.y1 - fr.y0) * c->p.nz;
     return FDTD_OK;
 }
@@ -466,6 +477,29 @@ int fdtd_set_tile(fdtd_ctx* c, int32_t rows, int32_t zchunk) {
         c->rows = rows;
         c->zchunk = zchunk;
         ensure_partials(c);
+    });
+}
+
+int fdtd_set_time_block(fdtd_ctx* c, int32_t steps, int32_t rows, int32_t zchunk) {
+    if (!c) return FDTD_EINVAL;
+    if (c->batch_owned) {
+        c->err = "instance is stepped by its batch";
+        return FDTD_ESTATE;
+    }
+    return guarded(c, [&] {
+        need(steps == 1 || steps == 2, "steps must be 1 or 2");
+        need(rows == 2 || rows == 4, "rows must be 2 or 4");
+        need(zchunk >= 0 && zchunk <= c->p.nz, "zchunk out of range");
+        if (steps == 2 && !c->mid) c->mid = dalloc<float>(c, 6 * (size_t)c->p.fstride);
+        if (steps == 1 && c->mid) {
+            check(hipStreamSynchronize(c->stream), "sync");
+            dfree(c, c->mid);
+            c->device_bytes -= (long long)(6 * (size_t)c->p.fstride * sizeof(float));
+            c->mid = nullptr;
+        }
+        c->time_block = steps;
+        c->tb_rows = rows;
+        c->tb_zchunk = zchunk;
     });
 }
 

@@ -106,6 +106,10 @@ struct fdtd_ctx {
     int4* ftiles = nullptr;         // fused frame tiles (0, x0, y0, z chunk)
     int nftiles = 0, ftile_cap = 0, fblocks = 0, fcz = 0, frows = 0;
     bfdtd::Frame ftile_rect{0, 0, 0, 0};
+    // two-step interior kernel (time_block 2) and the frame's intermediate
+    // fields (six components, one parity's layout)
+    int time_block = 1, tb_rows = 4, tb_zchunk = 0;
+    float* mid = nullptr;
     bool batch_owned = false;      // stepped by an fdtd_batch
     EventTimer* timer = nullptr;
     std::string err;
@@ -285,6 +289,63 @@ inline hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, 
     }
     return launch_split_frame(q, n, parity, fr, epart ? epart + off : nullptr, c->stream,
                               c->timer);
+}
+
+// Pairs of steps go through the two-step interior kernel when it is
+// selected, the fused kernel is in use, the grid has room for its interior,
+// and neither the energy record nor a plane record is wanted.
+inline Frame two_step_rect(const fdtd_ctx* c) {
+    if (c->time_block != 2 || !c->mid || c->kernel == FDTD_KERNEL_SPLIT || c->p.periodic ||
+        (c->mask & FDTD_DIAG_ENERGY) || c->p.rec)
+        return Frame{0, 0, 0, 0};
+    return fused2_interior_rect(c->p, c->tb_rows);
+}
+
+// Steps n and n + 1 in one pass over the interior: the two-step kernel
+// reads parity par (buffers A) and writes par ^ 1 (B) inside rectangle R.
+// The frame around R goes through the split kernels in four passes with
+// the intermediate buffer C:
+//   E^{n+1}: A -> C on the frame and a one-cell ring inside R (the ring
+//            is not accumulated: the interior kernel owns it);
+//   H^{n+3/2}: A, C -> C on the frame and the ring's right and top sides;
+//   E^{n+2}: C -> B on the frame;  H^{n+5/2}: C, B -> B on the frame (its
+//            E neighbours on R's edge are the interior kernel's).
+// The CPML memories go par -> par ^ 1 -> par; the two memory buffers then
+// trade places so that the newest is the one of parity par ^ 1.
+inline void launch_pair(fdtd_ctx* c, long long n) {
+    const Frame R = two_step_rect(c);
+    const int par = c->parity;
+    Problem q = c->p;
+    q.plane = c->plane;
+    const unsigned dm = c->mask & 7u;
+    const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
+    const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
+    check(launch_fused2_interior(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->stream,
+                                 c->timer),
+          "two-step interior launch");
+    Problem a = q;
+    a.fbase[par ^ 1] = c->mid;
+    a.diag_mask = m0;
+    check(launch_split_pass(a, n, par, Frame{R.x0 + 1, R.x1 - 1, R.y0 + 1, R.y1 - 1}, R, false,
+                            c->stream, c->timer),
+          "frame pass");
+    check(launch_split_pass(a, n, par, Frame{R.x0, R.x1 - 1, R.y0, R.y1 - 1}, Frame{0, 0, 0, 0},
+                            true, c->stream, c->timer),
+          "frame pass");
+    Problem b = q;
+    b.fbase[0] = c->mid;
+    b.fbase[1] = q.fbase[par ^ 1];
+    b.pbase[0] = q.pbase[par ^ 1];
+    b.pbase[1] = q.pbase[par];
+    b.diag_mask = m1;
+    check(launch_split_pass(b, n + 1, 0, R, Frame{0, 0, 0, 0}, false, c->stream, c->timer),
+          "frame pass");
+    check(launch_split_pass(b, n + 1, 0, R, Frame{0, 0, 0, 0}, true, c->stream, c->timer),
+          "frame pass");
+    std::swap(c->p.pbase[0], c->p.pbase[1]);
+    c->count += (m0 != 0) + (m1 != 0);
+    c->parity ^= 1;
+    c->step += 2;
 }
 
 }  // namespace bfdtd

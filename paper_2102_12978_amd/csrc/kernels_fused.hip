@@ -192,10 +192,12 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, long long n, int 
 #pragma unroll
     for (int r = 0; r < TY; ++r) {
         const float hxr = bcast(g, Hq::R_HX + 1 + r);
-        float vy = bcast(g, Hq::R_EY + r) + p.sz * (hxr - hxkm[r]) -
-                   p.sx * (bcast(g, Hq::R_HZ + r) - hz[r + 1]);
-        float vz = bcast(g, Hq::R_EZ + r) + p.sx * (bcast(g, Hq::R_HY + r) - hy[r]) -
-                   p.sy * (hxr - hx_prev);
+        // same association as e_plane (E + (curl)), so the column matches the
+        // value its own segment forms bit for bit
+        float vy = bcast(g, Hq::R_EY + r);
+        vy += p.sz * (hxr - hxkm[r]) - p.sx * (bcast(g, Hq::R_HZ + r) - hz[r + 1]);
+        float vz = bcast(g, Hq::R_EZ + r);
+        vz += p.sx * (bcast(g, Hq::R_HY + r) - hy[r]) - p.sy * (hxr - hx_prev);
         if (slot_h[r] >= 0) {
             const float2* a = p.amp + (size_t)slot_h[r] * 6;
             vy += cmul_re(a[EY], pt0);

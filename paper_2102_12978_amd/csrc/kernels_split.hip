@@ -55,13 +55,17 @@ __device__ __forceinline__ bool frame_column(const Frame& fr, int nx, int ny, un
     return true;
 }
 
+// nd: cells inside this rectangle are updated without the plane
+// accumulation (cells that another kernel owns and accumulates).
 __global__ void __launch_bounds__(BT)
-split_e_kernel(Problem p, long long n, int par, Frame fr, long long ncols, double* epart) {
+split_e_kernel(Problem p, long long n, int par, Frame fr, long long ncols, double* epart,
+               Frame nd) {
     int i = 0, j = 0;
     const int k = blockIdx.y;
     const unsigned col = blockIdx.x * BT + threadIdx.x;
     const bool inside = col < (unsigned long long)ncols && frame_column(fr, p.nx, p.ny, col, &i, &j);
-    const double e2 = inside ? e_point(p, n, par, i, j, k, p.diag_mask) : 0.0;
+    const bool owned = !(i >= nd.x0 && i < nd.x1 && j >= nd.y0 && j < nd.y1);
+    const double e2 = inside ? e_point(p, n, par, i, j, k, owned ? p.diag_mask : 0) : 0.0;
     if (epart) block_energy(e2, epart + (size_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
@@ -94,12 +98,28 @@ hipError_t launch_split_frame(const Problem& p, long long n, int parity, const F
     dim3 grid((unsigned)((nc + BT - 1) / BT), p.nz, 1);
     const size_t nb = (size_t)grid.x * grid.y;
     if (timer) timer->mark(fr.x1 > 0 ? "frame_e" : "split_e");
-    hipLaunchKernelGGL(split_e_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, epart);
+    hipLaunchKernelGGL(split_e_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, epart,
+                       Frame{0, 0, 0, 0});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (timer) timer->mark(fr.x1 > 0 ? "frame_h" : "split_h");
     hipLaunchKernelGGL(split_h_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc,
                        epart ? epart + nb : nullptr);
+    if (timer) timer->mark(nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_pass(const Problem& p, long long n, int parity, const Frame& fr,
+                             const Frame& nodiag, bool h_pass, hipStream_t s, LaunchTimer* timer) {
+    const long long nc = frame_columns(p, fr);
+    if (nc == 0) return hipSuccess;
+    dim3 grid((unsigned)((nc + BT - 1) / BT), p.nz, 1);
+    if (timer) timer->mark(h_pass ? "frame2_h" : "frame2_e");
+    if (h_pass)
+        hipLaunchKernelGGL(split_h_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, nullptr);
+    else
+        hipLaunchKernelGGL(split_e_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, nullptr,
+                           nodiag);
     if (timer) timer->mark(nullptr);
     return hipGetLastError();
 }

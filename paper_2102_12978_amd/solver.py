@@ -195,6 +195,11 @@ class Solver:
     def set_frame(self, kind, xalign=32, rows=2):
         self._c(self._lib.fdtd_set_frame(self._ctx, int(kind), int(xalign), int(rows)))
 
+    def set_time_block(self, steps, rows=4, zchunk=0):
+        """Steps per pass over the interior: 1, or 2 (the two-step kernel
+        with tiles of `rows` rows and z chunks of `zchunk` planes)."""
+        self._c(self._lib.fdtd_set_time_block(self._ctx, int(steps), int(rows), int(zchunk)))
+
     def profile(self, on=True):
         self._c(self._lib.fdtd_profile_enable(self._ctx, 1 if on else 0))
 

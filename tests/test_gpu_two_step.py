@@ -1,0 +1,163 @@
+"""Two-step interior kernel (temporal blocking, fdtd_set_time_block).
+
+Every cell is computed with the one-step kernels' expressions in the same
+order, so a two-step run must equal a one-step run bit for bit: fields, CPML
+memories and the plane sums. The cases cross several 60-cell tiles and row
+groups with ragged frames, z chunks that do and do not divide nz, odd step
+counts (the last step runs alone), sources, CPML, a seeded random start and
+the 768x768x255 benchmark grid; one case is also checked against the FP64
+oracle."""
+import numpy as np
+import pytest
+
+from paper_2102_12978_amd import _lib as L
+from paper_2102_12978_amd import workloads as W
+from tests import cases
+from tests import gpu_cases as GC
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _solvers(w, rows, zchunk, inject=True):
+    one = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0, inject=inject)
+    two = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0, inject=inject)
+    two.set_time_block(2, rows, zchunk)
+    assert two.info().time_block == 2
+    return one, two
+
+
+def _arrays(w):
+    return list(range(6)) + (list(GC.PSI) if w.npml > 0 else [])
+
+
+def _assert_identical(one, two, w, label):
+    for q in _arrays(w):
+        a, b = one.get_state(q), two.get_state(q)
+        bad = np.count_nonzero(a.view(np.uint32) != b.view(np.uint32))
+        if bad:
+            idx = np.argwhere(a.view(np.uint32) != b.view(np.uint32))[:4]
+            print(f"  {label}: array {q}: {bad} cells differ, first {idx.tolist()}", flush=True)
+        assert bad == 0, f"{label}: array {q}"
+
+
+def _random_start(solvers, w, seed):
+    rng = np.random.default_rng(seed)
+    s0 = solvers[0]
+    for q in _arrays(w):
+        a = rng.uniform(-1.0, 1.0, size=s0.state_shape(q)).astype(np.float32)
+        if q in (L.EX, L.EY, L.EZ):
+            # E held on the x = 0 / y = 0 walls
+            if q in (L.EY, L.EZ):
+                a[:, :, 0] = 0.0
+            if q in (L.EX, L.EZ):
+                a[:, 0, :] = 0.0
+        for s in solvers:
+            s.set_state(q, a)
+
+
+@pytest.mark.parametrize("rows,zchunk,steps", [(4, 0, 40), (2, 0, 41), (4, 5, 40), (2, 7, 13),
+                                                (4, 16, 2)])
+def test_bit_identical_with_source(rows, zchunk, steps):
+    w = W.parity_mid()
+    one, two = _solvers(w, rows, zchunk)
+    g = cases.oracle_grid(w)
+    for s in (one, two):
+        s.set_diagnostics(g.nz // 2, 5, L.DIAG_EX2 | L.DIAG_EY2 | L.DIAG_EZ2)
+        s.step(steps)
+    assert two.info().step == steps
+    _assert_identical(one, two, w, f"rows={rows} zchunk={zchunk} steps={steps}")
+    assert one.fluence_count() == two.fluence_count() == max(0, steps - 5)
+    for q in (L.DIAG_EX2, L.DIAG_EY2, L.DIAG_EZ2):
+        assert np.array_equal(one.fluence(q), two.fluence(q))
+    one.close()
+    two.close()
+
+
+@pytest.mark.parametrize("maker,rows,zchunk", [(W.parity_wide, 4, 5), (W.parity_wide, 2, 0),
+                                               (W.parity_small, 4, 16), (W.parity_gauss, 2, 3)])
+def test_bit_identical_random_start(maker, rows, zchunk):
+    w = maker()
+    one, two = _solvers(w, rows, zchunk)
+    _random_start((one, two), w, seed=17)
+    for s in (one, two):
+        s.step(6)
+    _assert_identical(one, two, w, f"{w.name} rows={rows} zchunk={zchunk}")
+    # and on from there, with the parities of the two runs now swapped once
+    for s in (one, two):
+        s.step(3)
+    _assert_identical(one, two, w, f"{w.name} +3 steps")
+    one.close()
+    two.close()
+
+
+def test_against_oracle():
+    w = W.parity_mid()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0)
+    s.set_time_block(2, 4, 0)
+    s.step(w.steps)
+    g, st = GC.oracle_run(w, w.steps)
+    rel = GC.rel_l2(s.fields(), [st.f[c] for c in GC.COMPS])
+    print(f"  two-step {w.steps} steps vs FP64 oracle: rel-L2 {rel:.2e}", flush=True)
+    assert rel <= TOL
+    s.close()
+
+
+def test_fallbacks():
+    """Energy diagnostic on, a grid too small for the two-step interior, and
+    the split kernel: pairs run as single steps, with the same results."""
+    w = W.parity_mid()
+    one, two = _solvers(w, 4, 0)
+    g = cases.oracle_grid(w)
+    for s in (one, two):
+        s.set_diagnostics(g.nz // 2, 0, L.DIAG_EY2 | L.DIAG_ENERGY)
+        s.step(10)
+    assert one.energy() == two.energy()
+    _assert_identical(one, two, w, "energy on")
+    one.close()
+    two.close()
+    w0 = W.config0()
+    w0.steps = 12
+    one, two = _solvers(w0, 4, 0)
+    assert two.info().interior_cells == 0 or two.info().time_block == 2
+    for s in (one, two):
+        s.step(w0.steps)
+    _assert_identical(one, two, w0, "small grid")
+    one.close()
+    two.close()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
+    s.set_time_block(2, 2, 0)
+    r = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT)
+    for x in (s, r):
+        x.step(6)
+    _assert_identical(r, s, w, "split kernel")
+    s.set_time_block(1, 4, 0)
+    assert s.info().time_block == 1
+    s.close()
+    r.close()
+
+
+def test_bad_arguments():
+    w = W.parity_small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    for args in ((3, 4, 0), (0, 4, 0), (2, 8, 0), (2, 4, -1), (2, 4, 10**6)):
+        with pytest.raises(L.FdtdError) as e:
+            s.set_time_block(*args)
+        assert e.value.code == L.EINVAL
+    s.close()
+
+
+def test_benchmark_grid_bit_identical():
+    """768x768x255 (the benchmark grid): random fields and CPML memories,
+    antenna on, four steps with the two-step kernel (4 rows, z chunks of 32)
+    against four one-step launches."""
+    w = W.config2()
+    one, two = _solvers(w, 4, 32)
+    print(f"  {w.name}: random state", flush=True)
+    _random_start((one, two), w, seed=23)
+    for s in (one, two):
+        s.step(4)
+    _assert_identical(one, two, w, "768 grid")
+    one.close()
+    two.close()
