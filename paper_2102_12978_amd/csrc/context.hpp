@@ -302,14 +302,14 @@ inline Frame two_step_rect(const fdtd_ctx* c) {
 }
 
 // Steps n and n + 1 in one pass over the interior: the two-step kernel
-// reads parity par (buffers A) and writes par ^ 1 (B) inside rectangle R.
-// The frame around R goes through the split kernels in four passes with
-// the intermediate buffer C:
-//   E^{n+1}: A -> C on the frame and a one-cell ring inside R (the ring
-//            is not accumulated: the interior kernel owns it);
-//   H^{n+3/2}: A, C -> C on the frame and the ring's right and top sides;
-//   E^{n+2}: C -> B on the frame;  H^{n+5/2}: C, B -> B on the frame (its
-//            E neighbours on R's edge are the interior kernel's).
+// reads parity par (buffers A) and writes par ^ 1 (B) inside rectangle R,
+// and leaves in the intermediate buffer C the values of R's edge cells
+// that the frame needs. The frame around R goes through the split kernels
+// in four passes:
+//   E^{n+1}: A -> C;   H^{n+3/2}: A, C -> C (E^{n+1} of R's low edges from
+//   the interior kernel);   E^{n+2}: C -> B (H^{n+3/2} of R's high edges
+//   from the interior kernel);   H^{n+5/2}: C, B -> B (E^{n+2} of R's low
+//   edges, in B, from the interior kernel).
 // The CPML memories go par -> par ^ 1 -> par; the two memory buffers then
 // trade places so that the newest is the one of parity par ^ 1.
 inline void launch_pair(fdtd_ctx* c, long long n) {
@@ -320,28 +320,23 @@ inline void launch_pair(fdtd_ctx* c, long long n) {
     const unsigned dm = c->mask & 7u;
     const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
     const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
-    check(launch_fused2_interior(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->stream,
+    check(launch_fused2_interior(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->mid, c->stream,
                                  c->timer),
           "two-step interior launch");
+    const Frame none{0, 0, 0, 0};
     Problem a = q;
     a.fbase[par ^ 1] = c->mid;
     a.diag_mask = m0;
-    check(launch_split_pass(a, n, par, Frame{R.x0 + 1, R.x1 - 1, R.y0 + 1, R.y1 - 1}, R, false,
-                            c->stream, c->timer),
-          "frame pass");
-    check(launch_split_pass(a, n, par, Frame{R.x0, R.x1 - 1, R.y0, R.y1 - 1}, Frame{0, 0, 0, 0},
-                            true, c->stream, c->timer),
-          "frame pass");
+    check(launch_split_pass(a, n, par, R, none, false, c->stream, c->timer), "frame pass");
+    check(launch_split_pass(a, n, par, R, none, true, c->stream, c->timer), "frame pass");
     Problem b = q;
     b.fbase[0] = c->mid;
     b.fbase[1] = q.fbase[par ^ 1];
     b.pbase[0] = q.pbase[par ^ 1];
     b.pbase[1] = q.pbase[par];
     b.diag_mask = m1;
-    check(launch_split_pass(b, n + 1, 0, R, Frame{0, 0, 0, 0}, false, c->stream, c->timer),
-          "frame pass");
-    check(launch_split_pass(b, n + 1, 0, R, Frame{0, 0, 0, 0}, true, c->stream, c->timer),
-          "frame pass");
+    check(launch_split_pass(b, n + 1, 0, R, none, false, c->stream, c->timer), "frame pass");
+    check(launch_split_pass(b, n + 1, 0, R, none, true, c->stream, c->timer), "frame pass");
     std::swap(c->p.pbase[0], c->p.pbase[1]);
     c->count += (m0 != 0) + (m1 != 0);
     c->parity ^= 1;

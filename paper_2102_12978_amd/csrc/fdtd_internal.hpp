@@ -140,10 +140,13 @@ hipError_t launch_split_pass(const Problem& p, long long n, int parity, const Fr
 
 // Two-step fused interior kernel (kernels_fused2.hip); rows per wavefront 2
 // or 4. The interior it stores, and one launch advancing it from step n to
-// n + 2 (mask0 / mask1: plane accumulation of steps n and n + 1).
+// n + 2 (mask0 / mask1: plane accumulation of steps n and n + 1); mid: the
+// intermediate fields, where it leaves E^{n+1} of the rectangle's low-x /
+// low-y edge cells and H^{n+3/2} of its high-x / high-y edge cells.
 Frame fused2_interior_rect(const Problem& p, int rows);
 hipError_t launch_fused2_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
-                                  int mask0, int mask1, hipStream_t s, LaunchTimer* timer);
+                                  int mask0, int mask1, float* mid, hipStream_t s,
+                                  LaunchTimer* timer);
 
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 

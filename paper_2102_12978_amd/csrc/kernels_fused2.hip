@@ -11,9 +11,9 @@
 // marches along z. The intermediate step is formed in registers on every
 // lane and every row it can be formed on, so the second step needs nothing
 // from other wavefronts:
-//   x: neighbours move between lanes with cross-lane shuffles; lanes 0-1 and
-//      62-63 are halo, the wavefront stores lanes 2..61 (60 cells), and the
-//      tiles advance by 60 cells.
+//   x: neighbours move between lanes with DPP wavefront shifts; lanes 0-1
+//      and 62-63 are halo, the wavefront stores at most lanes 2..61 (60
+//      cells), and the tiles advance by 60 cells.
 //   y: E^{n+1} is formed on rows -1 .. TY+1, H^{n+3/2} on rows -1 .. TY,
 //      E^{n+2} on rows 0 .. TY, H^{n+5/2} on the TY stored rows.
 //   z: at plane q the pipeline forms E^{n+1}(q), H^{n+3/2}(q-1),
@@ -22,7 +22,9 @@
 // The cells a wavefront forms must all be regular (no wall, no CPML), which
 // bounds the interior to x0 - 1, j0 - 1 >= m + 1 and x0 + 61, j0 + TY + 1 <=
 // n - npml - 1. The frame around it is advanced by the split kernels in
-// four passes through an intermediate buffer (context.hpp).
+// four passes through an intermediate buffer (context.hpp); the kernel
+// writes into that buffer the intermediate values of its edge cells that
+// those passes read.
 //
 // Addresses: a wave-uniform 64-bit base (component, plane, row, tile
 // origin) in scalar registers plus the lane's byte offset, so every size
@@ -51,18 +53,23 @@ __device__ __forceinline__ gptr<char> uniform(gptr<T> q) {
 }
 
 struct Interior2 {
-    int x_org, y_org, nseg, nrow, ncz, cz;
+    int x_org, x_end, y_org, nseg, nrow, ncz, cz;
 };
 
+// x: [x_org, x_end) on 32-cell (128-byte) boundaries, so that the frame's x
+// strips are whole lines; tiles of 60 cells from x_org, the last one shifted
+// left to end at x_end (it stores only the cells the others leave).
+// Every cell a wavefront forms lies in [m + 1, n - npml - 1] in x and y.
 Interior2 interior2(const Problem& p, int rows, int zchunk) {
-    Interior2 I{0, 0, 0, 0, 0, 0};
+    Interior2 I{0, 0, 0, 0, 0, 0, 0};
     if (p.periodic) return I;
     const int m = p.npml > 0 ? p.npml : 1;
     const int hi_x = p.nx - p.npml - 1, hi_y = p.ny - p.npml - 1;
-    I.x_org = m + 2;
+    I.x_org = (m + 2 + 31) / 32 * 32;
+    I.x_end = (hi_x - 1) / 32 * 32;
     I.y_org = m + 2;
-    const int sx = hi_x - (OWN + 1) - I.x_org, sy = hi_y - (rows + 1) - I.y_org;
-    I.nseg = sx >= 0 ? sx / OWN + 1 : 0;
+    const int sy = hi_y - (rows + 1) - I.y_org;
+    I.nseg = I.x_end - I.x_org >= OWN ? (I.x_end - I.x_org + OWN - 1) / OWN : 0;
     I.nrow = sy >= 0 ? sy / rows + 1 : 0;
     I.cz = zchunk > 0 ? std::min(zchunk, p.nz) : p.nz;
     I.ncz = (p.nz + I.cz - 1) / I.cz;
@@ -74,11 +81,22 @@ int group_count2(const Interior2& I) {
     return I.nseg * ((I.nrow + WAVES - 1) / WAVES) * I.ncz;
 }
 
+// Cross-lane moves by one lane (DPP wavefront shifts: a VALU operand
+// modifier, no LDS round trip). Lanes without a source keep their own value.
+__device__ __forceinline__ float from_lower(float v) {   // lane l gets lane l - 1
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_upper(float v) {   // lane l gets lane l + 1
+    const int b = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false));
+}
+
 template <int TY>
 __global__ void __launch_bounds__(64 * WAVES)
 __attribute__((amdgpu_waves_per_eu(TY == 2 ? 3 : 2)))
 fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks_padded,
-                       int mask0, int mask1) {
+                       int mask0, int mask1, float* mid) {
     // ---- which tile: hardware block b runs on XCD b % 8 ----------------
     const int nrq = (I.nrow + WAVES - 1) / WAVES;
     const int lb = (blockIdx.x % 8) * (nblocks_padded / 8) + blockIdx.x / 8;
@@ -91,9 +109,18 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
     if (sy >= I.nrow) return;                                  // uniform per wavefront
     const int lane = threadIdx.x & 63;
     const int j0 = I.y_org + sy * TY;
-    const int xs = I.x_org + OWN * seg - 2;                    // x of lane 0
+    const bool last = seg == I.nseg - 1;
+    const int own_lo = I.x_org + OWN * seg;                    // stored x range
+    const int own_hi = last ? I.x_end : own_lo + OWN;
+    const int xs = last ? I.x_end - OWN - 2 : own_lo - 2;      // x of lane 0
     const int x = xs + lane;
-    const bool own = lane >= 2 && lane < 2 + OWN;
+    const bool own = x >= own_lo && x < own_hi;
+    // cells on the rectangle's edge whose intermediate values the frame
+    // passes read: E^{n+1} on the low-x / low-y edge, H^{n+3/2} on the
+    // high-x / high-y edge (uniform test first: most tiles have none)
+    const int y_end = I.y_org + TY * I.nrow;
+    const bool edge_lo = seg == 0 || sy == 0;
+    const bool edge_hi = last || sy == I.nrow - 1;
     const int nz = p.nz, nx = p.nx, ny = p.ny;
     const size_t plane = (size_t)ny * p.pitch;
     const gptr<const float> fo = G((const float*)p.fbase[par]);
@@ -111,6 +138,10 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
     };
     auto st = [&](int c, int kk, int r, float v) {
         __builtin_nontemporal_store(v, (gptr<float>)(uniform(fw + base(c, kk, r)) + lo4));
+    };
+    const gptr<float> fm = G(mid);
+    auto st_mid = [&](int c, int kk, int r, float v) {
+        *(gptr<float>)(uniform(fm + base(c, kk, r)) + lo4) = v;
     };
 
     const bool src = p.colmap != nullptr;
@@ -178,8 +209,8 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
             phase(kq, tE0, pt0, pt1);
 #pragma unroll
             for (int r = -1; r <= TY + 1; ++r) {
-                const float hz_im = __shfl_up(hz[O + r], 1, 64);
-                const float hy_im = __shfl_up(hy[O + r], 1, 64);
+                const float hz_im = from_lower(hz[O + r]);
+                const float hy_im = from_lower(hy[O + r]);
                 ex[O + r] += p.sy * (hz[O + r] - hz[O + r - 1]) - p.sz * (hy[O + r] - hpy[O + r]);
                 ez[O + r] += p.sx * (hy[O + r] - hy_im) - p.sy * (hx[O + r] - hx[O + r - 1]);
                 if (r <= TY)
@@ -196,6 +227,16 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
 #pragma unroll
             for (int r = 0; r < TY; ++r) accumulate(mask0, r, ex[O + r], ey[O + r], ez[O + r]);
         }
+        if (edge_lo && q >= kb && q < ke) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                if (own && (x == I.x_org || j0 + r == I.y_org)) {
+                    st_mid(EX, kq, r, ex[O + r]);
+                    st_mid(EY, kq, r, ey[O + r]);
+                    st_mid(EZ, kq, r, ez[O + r]);
+                }
+            }
+        }
 
         // ---- H^{n+3/2}(q-1), rows -1 .. TY (H_y from 0) --------------------
         float gx[TY + 4], gy[TY + 4], gz[TY + 4];
@@ -204,8 +245,8 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
             phase(kq1, tH0, qt0, qt1);
 #pragma unroll
             for (int r = -1; r <= TY; ++r) {
-                const float ey_ip = __shfl_down(e1y[O + r], 1, 64);
-                const float ez_ip = __shfl_down(e1z[O + r], 1, 64);
+                const float ey_ip = from_upper(e1y[O + r]);
+                const float ez_ip = from_upper(e1z[O + r]);
                 gx[O + r] = hpx[O + r] - (p.sy * (e1z[O + r + 1] - e1z[O + r]) -
                                           p.sz * (ey[O + r] - e1y[O + r]));
                 if (r >= 0)
@@ -222,6 +263,17 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
             }
         }
 
+        if (edge_hi && q - 1 >= kb && q - 1 < ke) {
+#pragma unroll
+            for (int r = 0; r < TY; ++r) {
+                if (own && (x == I.x_end - 1 || j0 + r == y_end - 1)) {
+                    st_mid(HX, kq1, r, gx[O + r]);
+                    st_mid(HY, kq1, r, gy[O + r]);
+                    st_mid(HZ, kq1, r, gz[O + r]);
+                }
+            }
+        }
+
         // ---- E^{n+2}(q-1), rows 0 .. TY (E_y to TY-1) ----------------------
         float fx[TY + 4], fy[TY + 4], fz[TY + 4];
         {
@@ -229,8 +281,8 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
             phase(kq1, tE1, pt0, pt1);
 #pragma unroll
             for (int r = 0; r <= TY; ++r) {
-                const float hz_im = __shfl_up(gz[O + r], 1, 64);
-                const float hy_im = __shfl_up(gy[O + r], 1, 64);
+                const float hz_im = from_lower(gz[O + r]);
+                const float hy_im = from_lower(gy[O + r]);
                 fx[O + r] = e1x[O + r];
                 fz[O + r] = e1z[O + r];
                 fx[O + r] += p.sy * (gz[O + r] - gz[O + r - 1]) - p.sz * (gy[O + r] - h1y[O + r]);
@@ -267,8 +319,8 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
             phase(kq2, tH1, qt0, qt1);
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
-                const float ey_ip = __shfl_down(e2y[O + r], 1, 64);
-                const float ez_ip = __shfl_down(e2z[O + r], 1, 64);
+                const float ey_ip = from_upper(e2y[O + r]);
+                const float ez_ip = from_upper(e2z[O + r]);
                 float vx = h1x[O + r] - (p.sy * (e2z[O + r + 1] - e2z[O + r]) -
                                          p.sz * (fy[O + r] - e2y[O + r]));
                 float vy = h1y[O + r] - (p.sz * (fx[O + r] - e2x[O + r]) -
@@ -320,14 +372,14 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
 
 template <int TY>
 hipError_t launch_rows2(const Problem& p, long long n, int parity, int zchunk, int mask0,
-                        int mask1, hipStream_t s, LaunchTimer* timer) {
+                        int mask1, float* mid, hipStream_t s, LaunchTimer* timer) {
     const Interior2 I = interior2(p, TY, zchunk);
     const int nb = group_count2(I);
     if (nb <= 0) return hipSuccess;
     const int nbp = (nb + 7) / 8 * 8;
     if (timer) timer->mark("fused2_interior");
     hipLaunchKernelGGL((fused2_interior_kernel<TY>), dim3(nbp), dim3(64 * WAVES), 0, s, p, n,
-                       parity, I, nbp, mask0, mask1);
+                       parity, I, nbp, mask0, mask1, mid);
     hipError_t e = hipGetLastError();
     if (timer) timer->mark(nullptr);
     return e;
@@ -338,13 +390,15 @@ hipError_t launch_rows2(const Problem& p, long long n, int parity, int zchunk, i
 Frame fused2_interior_rect(const Problem& p, int rows) {
     const Interior2 I = interior2(p, rows, 0);
     if (I.nseg <= 0) return Frame{0, 0, 0, 0};
-    return Frame{I.x_org, I.x_org + OWN * I.nseg, I.y_org, I.y_org + rows * I.nrow};
+    return Frame{I.x_org, I.x_end, I.y_org, I.y_org + rows * I.nrow};
 }
 
 hipError_t launch_fused2_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
-                                  int mask0, int mask1, hipStream_t s, LaunchTimer* timer) {
-    if (rows == 2) return launch_rows2<2>(p, n, parity, zchunk, mask0, mask1, s, timer);
-    if (rows == 4) return launch_rows2<4>(p, n, parity, zchunk, mask0, mask1, s, timer);
+                                  int mask0, int mask1, float* mid, hipStream_t s,
+                                  LaunchTimer* timer) {
+    if (!mid) return hipErrorInvalidValue;
+    if (rows == 2) return launch_rows2<2>(p, n, parity, zchunk, mask0, mask1, mid, s, timer);
+    if (rows == 4) return launch_rows2<4>(p, n, parity, zchunk, mask0, mask1, mid, s, timer);
     return hipErrorInvalidValue;
 }
 

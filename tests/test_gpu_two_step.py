@@ -76,7 +76,7 @@ def test_bit_identical_with_source(rows, zchunk, steps):
 
 
 @pytest.mark.parametrize("maker,rows,zchunk", [(W.parity_wide, 4, 5), (W.parity_wide, 2, 0),
-                                               (W.parity_small, 4, 16), (W.parity_gauss, 2, 3)])
+                                               (W.config4, 4, 16), (W.parity_gauss, 2, 3)])
 def test_bit_identical_random_start(maker, rows, zchunk):
     w = maker()
     one, two = _solvers(w, rows, zchunk)
