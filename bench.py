@@ -20,26 +20,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 BYTES_PER_CELL = 48            # read + write six FP32 field components
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_interior_768x768x255_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc", "kernels_fused.hip")
+CSRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc")
+# interior kernels: source file, committed PMC summary, cell-updates per cell and launch
+KERNELS = {
+    "fused_interior": ("kernels_fused.hip", "fused_interior_768x768x255_traffic.json", 1),
+    "fused2_interior": ("kernels_fused2.hip", "fused2_interior_768x768x255_traffic.json", 2),
+}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+def kernel_hash(name):
+    src = os.path.join(CSRC, KERNELS[name][0])
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(interior_cells):
-    """HBM bytes per fused-kernel launch from the committed rocprofv3 PMC
-    summary, or None when missing or taken on another kernel source."""
+def measured_traffic(name):
+    """HBM bytes per launch of an interior kernel from the committed
+    rocprofv3 PMC summary, or None when missing or taken on another source."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(os.path.join(ROOT, "profiles", KERNELS[name][1])))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash():
+    if t.get("kernel_sha256_16") != kernel_hash(name):
         return None
     return t.get("bytes_per_launch")
 
@@ -220,6 +225,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--rows", type=int, default=0, help="fix the tile rows (skips autotune)")
     ap.add_argument("--zchunk", type=int, default=0, help="z chunk with --rows")
+    ap.add_argument("--time-block", type=int, default=0,
+                    help="fix the steps per interior pass (1 or 2)")
+    ap.add_argument("--tb-rows", type=int, default=4, help="two-step kernel rows")
+    ap.add_argument("--tb-zchunk", type=int, default=32, help="two-step kernel z chunk")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     args = ap.parse_args()
@@ -246,7 +255,11 @@ def main():
         s.set_tile(args.rows, args.zchunk)
     elif not args.no_tune:
         rows, zc = s.autotune(3)
-        log(f"[bench] autotuned tile: rows={rows} zchunk={zc}")
+        it = s.info()
+        log(f"[bench] autotuned: one-step tile rows={rows} zchunk={zc}; steps per pass "
+            f"{it.time_block} (two-step tile rows={it.tb_rows} zchunk={it.tb_zchunk})")
+    if args.time_block:
+        s.set_time_block(args.time_block, args.tb_rows, args.tb_zchunk)
     s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -268,18 +281,26 @@ def main():
     log(f"[bench] {args.steps} steps in {total_ms:.1f} ms -> {value:.1f} Gcell/s; "
         f"kernels: {prof}")
 
-    kin = prof.get("fused_interior")
+    # the dominant kernel: the interior kernel that ran (the two-step one
+    # when pairs of steps go through it)
+    kname = next((k for k in ("fused2_interior", "fused_interior") if k in prof), None)
     roof = None
-    if kin:
+    if kname:
+        kin = prof[kname]
         avg_ms = kin[1] / kin[0]
+        # algorithmic bytes: one read and one write of the six components of
+        # every interior cell per launch (a two-step launch advances them twice)
         bytes_launch = BYTES_PER_CELL * info.interior_cells
         achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic(info.interior_cells)
+        upd = KERNELS[kname][2]
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "fused_interior",
+                "traffic": measured_traffic(kname), "kernel": kname,
                 "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": info.interior_cells,
-                "bytes_per_launch": bytes_launch}
+                "cell_updates_per_launch": upd * info.interior_cells,
+                "bytes_per_launch": bytes_launch,
+                # the rate a one-step kernel would need for the same throughput
+                "one_step_equivalent_gbs": round(upd * achieved, 1)}
     step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
     if roof:
         # what a kernel with no arithmetic reaches on the same GPU (context for frac)
@@ -303,8 +324,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "768x768x256 (z fitted to 255) Yee grid, dx=lambda/24, "
                                "theta=20deg, order-2 Bessel antenna R=320dx, 16-cell CPML",
-                   "cells": cells, "tile_rows": info.tile_rows,
-                   "tile_zchunk": info.tile_zchunk},
+                   "cells": cells, "steps_per_pass": info.time_block,
+                   "tile_rows": info.tb_rows if info.time_block == 2 else info.tile_rows,
+                   "tile_zchunk": info.tb_zchunk if info.time_block == 2 else info.tile_zchunk},
         "step_hbm_fraction": round(step_gbs / HBM_PEAK_GBS, 4),
         "kernels_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()},
         "roofline": roof,

@@ -150,6 +150,8 @@ typedef struct fdtd_info {
     int32_t xalign;              /* interior x origin multiple (32 or 64)     */
     int32_t frame_rows;          /* rows per fused frame tile (2 or 4)        */
     int32_t time_block;          /* steps per interior pass (1 or 2)          */
+    int32_t tb_rows;             /* two-step kernel: y rows per wavefront     */
+    int32_t tb_zchunk;           /* two-step kernel: z planes per chunk       */
 } fdtd_info;
 
 /* Library version string (static storage). */
@@ -271,7 +273,12 @@ int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
 int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchunk);
 
 /* Time candidate tile shapes and frame choices on the live problem (the state
- * is restored) and keep the fastest. *best_rows / *best_zchunk may be NULL. */
+ * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
+ * frames, and, when the grid has room for its interior and the device has
+ * the free memory, the two-step kernel (fdtd_set_time_block) at rows {4, 2}
+ * x z chunks {32, 16, 64, whole}. *best_rows / *best_zchunk (may be NULL)
+ * receive the one-step kernel's tile; fdtd_get_info reports whether the
+ * two-step kernel won (time_block) and its tile. */
 int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,
                   int32_t *best_zchunk);
 

@@ -51,7 +51,8 @@ class Info(ctypes.Structure):
                 ("tile_zchunk", ctypes.c_int32), ("step", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("interior_cells", ctypes.c_int64),
                 ("frame", ctypes.c_int32), ("xalign", ctypes.c_int32),
-                ("frame_rows", ctypes.c_int32), ("time_block", ctypes.c_int32)]
+                ("frame_rows", ctypes.c_int32), ("time_block", ctypes.c_int32),
+                ("tb_rows", ctypes.c_int32), ("tb_zchunk", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):

@@ -437,6 +437,8 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->xalign = c->xalign;
     out->frame_rows = c->frame_rows;
     out->time_block = c->time_block;
+    out->tb_rows = c->tb_rows;
+    out->tb_zchunk = c->tb_zchunk;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
     const Frame f2 = two_step_rect(c);
@@ -531,7 +533,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
     return guarded(c, [&] {
         need(steps_per_trial >= 1 && steps_per_trial <= 1000, "steps_per_trial out of range");
         need(c->kernel == FDTD_KERNEL_FUSED, "autotune applies to the fused kernel");
-        ensure_time_tables(c, c->step + 1);
+        ensure_time_tables(c, c->step + 2);
         // Trials read the live parity buffer and write the other one, which
         // the next real step overwrites: the state is left as it was.
         Problem q = c->p;
@@ -579,15 +581,73 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                 }
             }
         }
-        c->timer = static_cast<EventTimer*>(keep_timer);
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         c->rows = br;
         c->zchunk = bz;
         c->frame = bf;
         c->xalign = ba;
         c->frame_rows = bfr;
         ensure_partials(c);
+        // the two-step kernel (per step: half a pair), when the grid has room
+        // for its interior and the device for the intermediate fields
+        const size_t mid_bytes = 6 * (size_t)c->p.fstride * sizeof(float);
+        size_t free_b = 0, total_b = 0;
+        const bool had_mid = c->mid != nullptr;
+        bool try2 = !c->p.periodic && fused2_interior_rect(c->p, 4).x1 > 0;
+        if (try2 && !had_mid) {
+            try2 = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                   free_b > mid_bytes + ((size_t)1 << 30);
+            if (try2) c->mid = dalloc<float>(c, 6 * (size_t)c->p.fstride);
+        }
+        int bt = 1, btr = c->tb_rows, btz = c->tb_zchunk;
+        if (try2) {
+            const int keep_tb = c->time_block, keep_r = c->tb_rows, keep_z = c->tb_zchunk;
+            const int keep_mask = (int)c->mask;
+            c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
+            c->time_block = 2;
+            const int pairs = std::max(1, steps_per_trial / 2);
+            std::vector<int> chunks2 = {32, 16, 64, 0};
+            for (int rows : {4, 2}) {
+                for (int cz : chunks2) {
+                    if (cz > nz) continue;
+                    c->tb_rows = rows;
+                    c->tb_zchunk = cz;
+                    launch_pair(c, c->step, true);
+                    check(hipEventRecord(e0, c->stream), "event");
+                    for (int s = 0; s < pairs; ++s) launch_pair(c, c->step, true);
+                    check(hipEventRecord(e1, c->stream), "event");
+                    check(hipEventSynchronize(e1), "event");
+                    float ms = 0.f;
+                    check(hipEventElapsedTime(&ms, e0, e1), "event");
+                    const float per_trial = ms / (2.0f * pairs) * steps_per_trial;
+                    if (per_trial < best) {
+                        best = per_trial;
+                        bt = 2;
+                        btr = rows;
+                        btz = cz;
+                    }
+                }
+            }
+            c->mask = (unsigned)keep_mask;
+            c->time_block = keep_tb;
+            c->tb_rows = keep_r;
+            c->tb_zchunk = keep_z;
+        }
+        c->timer = static_cast<EventTimer*>(keep_timer);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (bt == 2) {
+            c->time_block = 2;
+            c->tb_rows = btr;
+            c->tb_zchunk = btz;
+        } else {
+            c->time_block = 1;
+            if (c->mid && !had_mid) {
+                check(hipStreamSynchronize(c->stream), "sync");
+                dfree(c, c->mid);
+                c->device_bytes -= (long long)mid_bytes;
+                c->mid = nullptr;
+            }
+        }
         if (best_rows) *best_rows = br;
         if (best_zchunk) *best_zchunk = bz;
     });

@@ -312,12 +312,15 @@ inline Frame two_step_rect(const fdtd_ctx* c) {
 //   edges, in B, from the interior kernel).
 // The CPML memories go par -> par ^ 1 -> par; the two memory buffers then
 // trade places so that the newest is the one of parity par ^ 1.
-inline void launch_pair(fdtd_ctx* c, long long n) {
+// trial: a timing run that leaves the state alone (it writes only parity
+// par ^ 1, the intermediate buffer and, in place, the par ^ 1 memories; no
+// plane sums, and the step count does not move).
+inline void launch_pair(fdtd_ctx* c, long long n, bool trial = false) {
     const Frame R = two_step_rect(c);
     const int par = c->parity;
     Problem q = c->p;
     q.plane = c->plane;
-    const unsigned dm = c->mask & 7u;
+    const unsigned dm = trial ? 0u : c->mask & 7u;
     const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
     const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
     check(launch_fused2_interior(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->mid, c->stream,
@@ -333,10 +336,11 @@ inline void launch_pair(fdtd_ctx* c, long long n) {
     b.fbase[0] = c->mid;
     b.fbase[1] = q.fbase[par ^ 1];
     b.pbase[0] = q.pbase[par ^ 1];
-    b.pbase[1] = q.pbase[par];
+    b.pbase[1] = trial ? q.pbase[par ^ 1] : q.pbase[par];
     b.diag_mask = m1;
     check(launch_split_pass(b, n + 1, 0, R, none, false, c->stream, c->timer), "frame pass");
     check(launch_split_pass(b, n + 1, 0, R, none, true, c->stream, c->timer), "frame pass");
+    if (trial) return;
     std::swap(c->p.pbase[0], c->p.pbase[1]);
     c->count += (m0 != 0) + (m1 != 0);
     c->parity ^= 1;

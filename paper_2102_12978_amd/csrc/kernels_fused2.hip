@@ -136,8 +136,10 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
     auto ld = [&](int c, int kk, int r) {
         return *(gptr<const float>)(uniform(fo + base(c, kk, r)) + lo4);
     };
+    // plain stores: a tile stores 60 cells of a row, so lines at tile edges
+    // are written by two tiles and merge in L2
     auto st = [&](int c, int kk, int r, float v) {
-        __builtin_nontemporal_store(v, (gptr<float>)(uniform(fw + base(c, kk, r)) + lo4));
+        *(gptr<float>)(uniform(fw + base(c, kk, r)) + lo4) = v;
     };
     const gptr<float> fm = G(mid);
     auto st_mid = [&](int c, int kk, int r, float v) {

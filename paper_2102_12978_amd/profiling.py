@@ -20,11 +20,17 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc", "kernels_fused.hip")
+CSRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc")
+KERNEL_SRC = os.path.join(CSRC, "kernels_fused.hip")
 
 
 def kernel_sha256_16(path=KERNEL_SRC):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def source_of(kernel):
+    """Source file of an interior kernel (by the name the counters carry)."""
+    return os.path.join(CSRC, "kernels_fused2.hip" if "fused2" in kernel else "kernels_fused.hip")
 
 
 def short_name(name):
@@ -79,7 +85,7 @@ def traffic(a):
     write_b = w_kib * 1024.0 * w_scale
     return {
         "kernel": a.kernel,
-        "kernel_sha256_16": kernel_sha256_16(),
+        "kernel_sha256_16": kernel_sha256_16(source_of(a.kernel)),
         "command": a.cmd,
         "dispatches": {"fetch": nf, "write": nw},
         "fetch_kib_per_dispatch": round(f_kib, 1),
