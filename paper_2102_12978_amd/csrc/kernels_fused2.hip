@@ -19,6 +19,8 @@
 //   z: at plane q the pipeline forms E^{n+1}(q), H^{n+3/2}(q-1),
 //      E^{n+2}(q-1) and H^{n+5/2}(q-2), keeping one plane of each in
 //      registers; a chunk [kb, ke) reads planes kb-2 .. ke+1 (z is periodic).
+//      A workgroup stacks four wavefronts in y that start every plane
+//      together (one barrier per plane).
 // The cells a wavefront forms must all be regular (no wall, no CPML), which
 // bounds the interior to x0 - 1, j0 - 1 >= m + 1 and x0 + 61, j0 + TY + 1 <=
 // n - npml - 1. The frame around it is advanced by the split kernels in
@@ -106,7 +108,10 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
     const int sy = ((lb / I.nseg) % nrq) * WAVES + w;
     const int kb = (lb / (I.nseg * nrq)) * I.cz;
     const int ke = min(kb + I.cz, p.nz);
-    if (sy >= I.nrow) return;                                  // uniform per wavefront
+    if (sy >= I.nrow) {                                        // uniform per wavefront
+        for (int q = kb - 2; q <= ke + 1; ++q) __syncthreads(); // the others' barriers
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int j0 = I.y_org + sy * TY;
     const bool last = seg == I.nseg - 1;
@@ -191,6 +196,10 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
     kq %= nz;
     int kq1 = 0, kq2 = 0;   // planes of q-1, q-2
     for (int q = kb - 2; q <= ke + 1; ++q) {
+        // The four wavefronts of the workgroup start each plane together, so
+        // the halo rows one loads are the rows its neighbour loads in the
+        // same window (every wavefront passes this barrier equally often).
+        __syncthreads();
         // ---- plane q of E^n and H^{n+1/2} --------------------------------
         float hx[TY + 4], hy[TY + 4], hz[TY + 4], ex[TY + 4], ey[TY + 4], ez[TY + 4];
 #pragma unroll
