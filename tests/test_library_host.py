@@ -97,3 +97,46 @@ def test_polarisation_constants_match_the_header():
                         ("FDTD_POL_Y_TM", L.POL_Y_TM), ("FDTD_POL_Z_TM", L.POL_Z_TM),
                         ("FDTD_FRAME_SPLIT", L.FRAME_SPLIT), ("FDTD_FRAME_FUSED", L.FRAME_FUSED)):
         assert f"#define {name} {value}" in text, name
+
+
+def test_time_block_setter_rejects_null_handle():
+    lib = L.load()
+    assert lib.fdtd_set_time_block(None, 2, 4, 0) == L.EINVAL
+
+
+# ctypes structure -> C type name in include/fdtd.h
+_STRUCTS = (("Grid", "fdtd_grid"), ("Injector", "fdtd_injector"), ("Info", "fdtd_info"),
+            ("KernelProfile", "fdtd_kernel_profile"), ("BatchInfo", "fdtd_batch_info"),
+            ("AdjointInfo", "fdtd_adjoint_info"))
+
+
+def test_ctypes_structures_match_the_header_layout(tmp_path):
+    """Size and every field offset of the binding's structures equal what a
+    C compiler makes of include/fdtd.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{L.HEADER}"',
+             'int main(void) {']
+    for py, c in _STRUCTS:
+        cls = getattr(L, py)
+        lines.append(f'  printf("{py} size %zu\\n", sizeof({c}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{py} {fname} %zu\\n", offsetof({c}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        py, key, val = line.split()
+        got[(py, key)] = int(val)
+    for py, _ in _STRUCTS:
+        cls = getattr(L, py)
+        assert got[(py, "size")] == ctypes.sizeof(cls), py
+        for fname, _ in cls._fields_:
+            assert got[(py, fname)] == getattr(cls, fname).offset, (py, fname)
