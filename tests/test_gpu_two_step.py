@@ -20,20 +20,21 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
 
-def _solvers(w, rows, zchunk, inject=True):
-    one = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0, inject=inject)
-    two = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0, inject=inject)
+def _solvers(w, rows, zchunk, inject=True, bc=None):
+    one = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, bc=bc, rows=4, zchunk=0, inject=inject)
+    two = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, bc=bc, rows=4, zchunk=0, inject=inject)
     two.set_time_block(2, rows, zchunk)
     assert two.info().time_block == 2
     return one, two
 
 
-def _arrays(w):
-    return list(range(6)) + (list(GC.PSI) if w.npml > 0 else [])
+def _arrays(w, s=None):
+    npml = s.npml if s is not None else w.npml
+    return list(range(6)) + (list(GC.PSI) if npml > 0 else [])
 
 
 def _assert_identical(one, two, w, label):
-    for q in _arrays(w):
+    for q in _arrays(w, one):
         a, b = one.get_state(q), two.get_state(q)
         bad = np.count_nonzero(a.view(np.uint32) != b.view(np.uint32))
         if bad:
@@ -45,7 +46,7 @@ def _assert_identical(one, two, w, label):
 def _random_start(solvers, w, seed):
     rng = np.random.default_rng(seed)
     s0 = solvers[0]
-    for q in _arrays(w):
+    for q in _arrays(w, s0):
         a = rng.uniform(-1.0, 1.0, size=s0.state_shape(q)).astype(np.float32)
         if q in (L.EX, L.EY, L.EZ):
             # E held on the x = 0 / y = 0 walls
@@ -90,6 +91,47 @@ def test_bit_identical_random_start(maker, rows, zchunk):
     _assert_identical(one, two, w, f"{w.name} +3 steps")
     one.close()
     two.close()
+
+
+def test_bit_identical_pec_walls():
+    """PEC walls instead of CPML (no memories; E held on the x = 0 / y = 0
+    walls): random start, antenna on, odd step count."""
+    w = W.parity_mid()
+    one, two = _solvers(w, 4, 9, bc=L.BC_PEC)
+    assert two.npml == 0 and two.info().time_block == 2
+    _random_start((one, two), w, seed=5)
+    for s in (one, two):
+        s.step(7)
+    _assert_identical(one, two, w, "PEC walls")
+    one.close()
+    two.close()
+
+
+def test_gradient_with_two_step_forward():
+    """The adjoint's checkpointed forward runs through fdtd_step, so with
+    the two-step kernel it runs in pairs (segments of 25 steps end with a
+    single step); the intensity and the sector gradient equal those of the
+    one-step forward bit for bit."""
+    from paper_2102_12978_amd.adjoint import SectorSensitivity
+    w = W.Workload("adj_120_m0", 120, 120, 10, 12.0, 30.0, 0, 40.0, 2.0, 6, 90,
+                   ramp_periods=2.0, extra={"sectors": 16, "checkpoint_every": 25})
+    rng = np.random.default_rng(21)
+    amp = 1.0 + 0.05 * rng.standard_normal(16)
+    ph = 0.1 * rng.standard_normal(16)
+    out = []
+    for tb in (1, 2):
+        sens = SectorSensitivity(w, window_begin=60)
+        if tb == 2:
+            sens.solver.set_time_block(2, 4, 0)
+            assert sens.solver.info().interior_cells > 0
+        ibar = sens.intensity(amp, ph)
+        dl = 1e-3 * np.cos(np.arange(ibar.size, dtype=np.float64)).reshape(ibar.shape)
+        ga, gp = sens.backward(dl)
+        out.append((ibar, ga, gp))
+        sens.close()
+    (i1, a1, p1), (i2, a2, p2) = out
+    assert np.array_equal(i1, i2)
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
 
 
 def test_against_oracle():
