@@ -174,6 +174,7 @@ def adjoint_measure(torch, stream):
     amp, ph = W.config4_sector_params(seed=2, sectors=256)
     sens = SectorSensitivity(w, stream=stream.cuda_stream)
     s = sens.solver
+    s.autotune(3)        # the tile and steps per pass used by both timings
     A = on_axis(sens.intensity(np.ones(256), np.zeros(256)).astype(np.float64))
     region, j0sq = central_lobe_target(sens)
     target = A * j0sq
@@ -201,6 +202,7 @@ def adjoint_measure(torch, stream):
     t_plain = min(plain()[0] for _ in range(3))
     t_grad = min(grad()[0] for _ in range(3))
     inf = sens.adj.info()
+    tb = s.info().time_block
     cells = s.nx * s.ny * s.nz
     sens.close()
     return {
@@ -213,6 +215,7 @@ def adjoint_measure(torch, stream):
         "grad_over_forward": round(t_grad / t_plain, 3),
         "checkpoints": inf.checkpoints, "recompute_steps": inf.recompute_steps,
         "adjoint_device_bytes": inf.device_bytes,
+        "forward_steps_per_pass": tb,
     }
 
 

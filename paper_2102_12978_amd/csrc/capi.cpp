@@ -543,9 +543,45 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         std::vector<int> chunks = {0};
         for (int d = 2; d <= 16; d *= 2)
             if (nz / d >= 8) chunks.push_back((nz + d - 1) / d);
+        {
+            int cus = 256;
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+            for (int rows : {4, 8}) {
+                const int dz = fused_default_zchunk(c->p, rows, c->xalign, cus);
+                if (std::find(chunks.begin(), chunks.end(), dz) == chunks.end())
+                    chunks.push_back(dz);
+            }
+        }
         hipEvent_t e0, e1;
         check(hipEventCreate(&e0), "event");
         check(hipEventCreate(&e1), "event");
+        // Milliseconds per step of `launch(steps)` (each call advancing
+        // `per_call` steps): one untimed call, then at least steps_per_trial
+        // steps, repeated with more steps until the timed span reaches 2 ms
+        // so that small grids are not timed on a handful of launches.
+        auto per_step = [&](auto&& launch, int per_call) {
+            launch();
+            int calls = std::max(1, steps_per_trial / per_call);
+            for (int round = 0; round < 3; ++round) {
+                check(hipEventRecord(e0, c->stream), "event");
+                for (int s = 0; s < calls; ++s) launch();
+                check(hipEventRecord(e1, c->stream), "event");
+                check(hipEventSynchronize(e1), "event");
+                float ms = 0.f;
+                check(hipEventElapsedTime(&ms, e0, e1), "event");
+                if (ms >= 2.0f || calls >= 1000 / per_call)
+                    return ms / (float)(calls * per_call);
+                calls = std::min(1000 / per_call,
+                                 (int)(calls * (2.5f / std::max(ms, 0.01f))) + 1);
+            }
+            check(hipEventRecord(e0, c->stream), "event");
+            for (int s = 0; s < calls; ++s) launch();
+            check(hipEventRecord(e1, c->stream), "event");
+            check(hipEventSynchronize(e1), "event");
+            float ms = 0.f;
+            check(hipEventElapsedTime(&ms, e0, e1), "event");
+            return ms / (float)(calls * per_call);
+        };
         float best = 1e30f;
         int br = c->rows, bz = c->zchunk, bf = c->frame, ba = c->xalign, bfr = c->frame_rows;
         LaunchTimer* keep_timer = c->timer;
@@ -562,14 +598,9 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                     c->rows = rows;
                     c->zchunk = cz;
                     ensure_frame_tiles(c);
-                    check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
-                    check(hipEventRecord(e0, c->stream), "event");
-                    for (int s = 0; s < steps_per_trial; ++s)
-                        check(launch_step(c, q, c->step, c->parity, nullptr), "trial");
-                    check(hipEventRecord(e1, c->stream), "event");
-                    check(hipEventSynchronize(e1), "event");
-                    float ms = 0.f;
-                    check(hipEventElapsedTime(&ms, e0, e1), "event");
+                    const float ms = per_step(
+                        [&] { check(launch_step(c, q, c->step, c->parity, nullptr), "trial"); },
+                        1);
                     if (ms < best) {
                         best = ms;
                         br = rows;
@@ -604,23 +635,15 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             const int keep_mask = (int)c->mask;
             c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
             c->time_block = 2;
-            const int pairs = std::max(1, steps_per_trial / 2);
             std::vector<int> chunks2 = {32, 16, 64, 0};
             for (int rows : {4, 2}) {
                 for (int cz : chunks2) {
                     if (cz > nz) continue;
                     c->tb_rows = rows;
                     c->tb_zchunk = cz;
-                    launch_pair(c, c->step, true);
-                    check(hipEventRecord(e0, c->stream), "event");
-                    for (int s = 0; s < pairs; ++s) launch_pair(c, c->step, true);
-                    check(hipEventRecord(e1, c->stream), "event");
-                    check(hipEventSynchronize(e1), "event");
-                    float ms = 0.f;
-                    check(hipEventElapsedTime(&ms, e0, e1), "event");
-                    const float per_trial = ms / (2.0f * pairs) * steps_per_trial;
-                    if (per_trial < best) {
-                        best = per_trial;
+                    const float ms = per_step([&] { launch_pair(c, c->step, true); }, 2);
+                    if (ms < best) {
+                        best = ms;
                         bt = 2;
                         btr = rows;
                         btz = cz;
