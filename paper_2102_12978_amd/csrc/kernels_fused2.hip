@@ -135,8 +135,10 @@ fused2_interior_kernel(Problem p, long long n, int par, Interior2 I, int nblocks
     auto base = [&](int c, int kk, int r) {
         return (size_t)c * fs + (size_t)kk * plane + (size_t)(j0 + r) * p.pitch + xs;
     };
-    // The uniform address is pinned to scalar registers so that each access
-    // is one load or store with a scalar base and the lane's 32-bit offset.
+    // The uniform address (component, plane, row, tile) is formed in scalar
+    // registers; each access adds the lane's byte offset to it. (Buffer
+    // instructions with a scalar descriptor save that add but measured
+    // slower here.)
     const unsigned lo4 = 4u * (unsigned)lane;
     auto ld = [&](int c, int kk, int r) {
         return *(gptr<const float>)(uniform(fo + base(c, kk, r)) + lo4);
