@@ -15,19 +15,19 @@
 using namespace bfdtd;
 
 namespace bfdtd {
-hipError_t launch_adjoint_h(const Problem& lam, int par, hipStream_t s);
-hipError_t launch_adjoint_e(const Problem& lam, int par, hipStream_t s);
-hipError_t launch_adjoint_inject(const Problem& lam, const float* g, const float* ey, float coef,
-                                 hipStream_t s);
-hipError_t launch_adjoint_gacc(const Problem& lam, const int* slot_i, const int* slot_j,
+hipError_t launch_adjoint_h(const Problem& lam, int par, const Frame& fr, hipStream_t s);
+hipError_t launch_adjoint_e(const Problem& lam, int par, const Frame& fr, hipStream_t s);
+hipError_t launch_adjoint_inject(const Problem& lam, int par, const float* g, const float* ey,
+                                 float coef, hipStream_t s);
+hipError_t launch_adjoint_gacc(const Problem& lam, int par, const int* slot_i, const int* slot_j,
                                int nslots, int first, float2 t, double2* G, hipStream_t s);
 }  // namespace bfdtd
 
 struct fdtd_adjoint {
     fdtd_ctx* c = nullptr;
     int every = 100;                    // checkpoint interval (steps)
-    Problem lam{};                      // λ: fields in fbase[0] (updated in place), ψ ping-pong
-    int lam_par = 0;
+    Problem lam{};                      // λ: fields and ψ ping-pong, like the forward state
+    int lam_par = 0;                    // parity of the current λ
     std::vector<void*> allocs;
     long long device_bytes = 0;
     // checkpoints of the forward state after s * every steps
@@ -88,9 +88,10 @@ size_t psi_bytes(const Problem& p) { return p.npml > 0 ? psi_total(p) * sizeof(f
 
 void clear_lambda(fdtd_adjoint* a) {
     hipStream_t s = a->c->stream;
-    check(hipMemsetAsync(a->lam.fbase[0], 0, field_bytes(a->lam), s), "clear");
-    for (int par = 0; par < 2; ++par)
+    for (int par = 0; par < 2; ++par) {
+        check(hipMemsetAsync(a->lam.fbase[par], 0, field_bytes(a->lam), s), "clear");
         if (psi_bytes(a->lam)) check(hipMemsetAsync(a->lam.pbase[par], 0, psi_bytes(a->lam), s), "clear");
+    }
     a->lam_par = 0;
 }
 
@@ -107,11 +108,60 @@ void sync_lambda_tables(fdtd_adjoint* a) {
     l.plane = a->plane;
 }
 
-void transposed_step(fdtd_adjoint* a) {   // source-free, no loss term
-    hipStream_t s = a->c->stream;
-    check(launch_adjoint_h(a->lam, a->lam_par, s), "adjoint H launch");
-    check(launch_adjoint_e(a->lam, a->lam_par, s), "adjoint E launch");
+float2 time_value(const fdtd_ctx* c, double steps);
+
+// One transposed step, λ of parity par -> par ^ 1. On the interior of the
+// forward context's fused kernel the transposed step is the forward Yee
+// step with S_x, S_y, S_z negated and no source (the Yee curls are each
+// other's transposes), so the fused interior kernel runs it there; the
+// transposed-CPML kernels take the frame (the whole grid for the split
+// kernel choice or the periodic test mode). With correlations, G picks up
+// the H components of λ before the step and the E components after its
+// H-part transpose (they are final once λ_E of parity par ^ 1 is formed).
+void reverse_step(fdtd_adjoint* a, bool correlate, long long m) {
+    fdtd_ctx* c = a->c;
+    hipStream_t s = c->stream;
+    const int par = a->lam_par;
+    Frame fr{0, 0, 0, 0};
+    if (c->kernel != FDTD_KERNEL_SPLIT && !a->lam.periodic) {
+        fr = fused_interior_rect(a->lam, c->rows, c->xalign);
+        if (fr.x1 > fr.x0) {
+            Problem q = a->lam;
+            q.sx = -q.sx;
+            q.sy = -q.sy;
+            q.sz = -q.sz;
+            q.colmap = nullptr;
+            q.fl = nullptr;
+            q.rec = nullptr;
+            q.diag_mask = 0;
+            q.plane = -1;
+            if (correlate)
+                check(launch_adjoint_gacc(a->lam, par, a->slot_i, a->slot_j, a->nslots, HX,
+                                          time_value(c, m + 1.5), a->G, s), "G (H)");
+            check(launch_fused_interior(q, 0, par, c->rows, c->zchunk, c->xalign, nullptr, s,
+                                        nullptr), "adjoint interior launch");
+            check(launch_adjoint_h(a->lam, par, fr, s), "adjoint H launch");
+            check(launch_adjoint_e(a->lam, par, fr, s), "adjoint E launch");
+            if (correlate)
+                check(launch_adjoint_gacc(a->lam, par ^ 1, a->slot_i, a->slot_j, a->nslots, EX,
+                                          time_value(c, m + 1.0), a->G, s), "G (E)");
+            a->lam_par ^= 1;
+            return;
+        }
+    }
+    if (correlate)
+        check(launch_adjoint_gacc(a->lam, par, a->slot_i, a->slot_j, a->nslots, HX,
+                                  time_value(c, m + 1.5), a->G, s), "G (H)");
+    check(launch_adjoint_h(a->lam, par, fr, s), "adjoint H launch");
+    if (correlate)
+        check(launch_adjoint_gacc(a->lam, par ^ 1, a->slot_i, a->slot_j, a->nslots, EX,
+                                  time_value(c, m + 1.0), a->G, s), "G (E)");
+    check(launch_adjoint_e(a->lam, par, fr, s), "adjoint E launch");
     a->lam_par ^= 1;
+}
+
+void transposed_step(fdtd_adjoint* a) {   // source-free, no loss term
+    reverse_step(a, false, 0);
 }
 
 void save_checkpoint(fdtd_adjoint* a, int q) {
@@ -190,8 +240,8 @@ float2 time_value(const fdtd_ctx* c, double steps) {
     return make_float2((float)re, (float)im);
 }
 
-// Host copy of one λ array (fields in the single in-place buffer, ψ of the
-// current parity), same host layouts as fdtd_get_state.
+// Host copy of one λ array (fields and ψ of the current parity), same host
+// layouts as fdtd_get_state.
 void state_copy(fdtd_adjoint* a, int which, float* host, int64_t n, bool to_host,
                 const Problem& p) {
     need(which >= FDTD_EX && which <= FDTD_PSI_HZY, "unknown state array");
@@ -207,7 +257,7 @@ void state_copy(fdtd_adjoint* a, int which, float* host, int64_t n, bool to_host
     hipStream_t s = a->c->stream;
     const size_t w = p.nx * sizeof(float), pb = p.pitch * sizeof(float);
     if (which <= FDTD_HZ) {
-        float* d = p.fbase[0] + which * p.fstride;
+        float* d = p.fbase[a->lam_par] + which * p.fstride;
         if (to_host)
             check(hipMemcpy2DAsync(host, w, d, pb, w, (size_t)p.nz * p.ny, hipMemcpyDeviceToHost, s), "copy");
         else
@@ -249,8 +299,7 @@ int fdtd_adjoint_create(fdtd_ctx* fwd, int32_t checkpoint_every, fdtd_adjoint** 
         const Problem& f = fwd->p;
         Problem& l = a->lam;
         l = f;
-        l.fbase[0] = aalloc<float>(a, 6 * field_elems(f));
-        l.fbase[1] = nullptr;
+        for (int par = 0; par < 2; ++par) l.fbase[par] = aalloc<float>(a, 6 * field_elems(f));
         for (int par = 0; par < 2; ++par)
             l.pbase[par] = f.npml > 0 ? aalloc<float>(a, psi_total(f)) : nullptr;
         l.fl = nullptr;
@@ -342,16 +391,10 @@ int fdtd_adjoint_backward(fdtd_adjoint* a, const float* dl_dI, int64_t n, int32_
             }
             for (long long m = n1 - 1; m >= n0; --m) {
                 if (m >= a->wbegin)
-                    check(launch_adjoint_inject(a->lam, a->g_dev,
+                    check(launch_adjoint_inject(a->lam, a->lam_par, a->g_dev,
                                                 a->rec + (size_t)(m - rb) * p.nx * p.ny, coef, s),
                           "inject");
-                check(launch_adjoint_gacc(a->lam, a->slot_i, a->slot_j, a->nslots, HX,
-                                          time_value(c, m + 1.5), a->G, s), "G (H)");
-                check(launch_adjoint_h(a->lam, a->lam_par, s), "adjoint H launch");
-                check(launch_adjoint_gacc(a->lam, a->slot_i, a->slot_j, a->nslots, EX,
-                                          time_value(c, m + 1.0), a->G, s), "G (E)");
-                check(launch_adjoint_e(a->lam, a->lam_par, s), "adjoint E launch");
-                a->lam_par ^= 1;
+                reverse_step(a, true, m);
             }
         }
         // sector gradients from the per-point correlations (host, double)

@@ -12,10 +12,15 @@
 // E components held by the PEC walls are not updated forward, so their μ is
 // zero and their λ_ψ passes through unchanged.
 //
-// The reverse step undoes the H part first, then the E part. Each kernel
-// updates the λ of the differenced fields in place (a cell only reads λ of
-// the other family and the old ψ) and writes the new λ_ψ to the other
-// parity. One thread per cell; grid (columns / 256, nz).
+// The reverse step undoes the H part first, then the E part. λ is
+// ping-ponged like the forward fields: the H-part transpose forms λ_E of
+// parity par ^ 1 from λ_E and λ_H of parity par, the E-part transpose forms
+// λ_H of parity par ^ 1 from λ_H of parity par and the new λ_E; the new λ_ψ
+// go to parity par ^ 1 as well. On cells away from walls and CPML this is
+// the forward Yee step with S_x, S_y, S_z negated and no source, which the
+// fused interior kernel runs (adjoint.cpp); these kernels take the frame
+// around that interior (or the whole grid). One thread per cell; grid
+// (frame columns / 256, nz).
 #include <hip/hip_runtime.h>
 
 #include "kernels_common.hpp"
@@ -26,14 +31,23 @@ namespace {
 
 constexpr int BT = 256;
 
+// vpar: parity of the other family's λ that the update reads (par for the
+// H-part transpose, par ^ 1, the new λ_E, for the E-part transpose).
 struct Lam {
     const Problem& p;
-    int par, i, j, k;
-    __device__ float* f(int c) const { return p.fbase[0] + c * p.fstride; }
+    int par, vpar, i, j, k;
+    __device__ gptr<const float> fo(int c) const {   // own family, parity par
+        return G((const float*)p.fbase[par]) + c * p.fstride;
+    }
+    __device__ gptr<float> fn(int c) const {         // own family, parity par ^ 1
+        return G(p.fbase[par ^ 1]) + c * p.fstride;
+    }
     __device__ size_t at(int ii, int jj, int kk) const {
         return ((size_t)kk * p.ny + jj) * p.pitch + ii;
     }
-    __device__ float v(int c, int ii, int jj, int kk) const { return f(c)[at(ii, jj, kk)]; }
+    __device__ float v(int c, int ii, int jj, int kk) const {
+        return (G((const float*)p.fbase[vpar]) + c * p.fstride)[at(ii, jj, kk)];
+    }
     __device__ gptr<const float> psi_old(int q) const { return pptr(p, par, q); }
     __device__ gptr<float> psi_new(int q) const { return pptr(p, par ^ 1, q); }
 };
@@ -72,10 +86,11 @@ __device__ __forceinline__ float dh_z(const Lam& L, int hc, float sign, int kk) 
     return sign * p.sz * L.v(hc, L.i, L.j, kk);
 }
 
-__global__ void __launch_bounds__(BT) adj_h_kernel(Problem p, int par) {
-    const int col = blockIdx.x * BT + threadIdx.x;
-    if (col >= p.nx * p.ny) return;
-    const Lam L{p, par, col % p.nx, col / p.nx, (int)blockIdx.y};
+__global__ void __launch_bounds__(BT) adj_h_kernel(Problem p, int par, Frame fr, long long ncols) {
+    int ci = 0, cj = 0;
+    const unsigned col = blockIdx.x * BT + threadIdx.x;
+    if (col >= (unsigned long long)ncols || !frame_column(fr, p.nx, p.ny, col, &ci, &cj)) return;
+    const Lam L{p, par, par, ci, cj, (int)blockIdx.y};
     const int i = L.i, j = L.j, k = L.k;
     const size_t id = L.at(i, j, k);
     // H terms: hx: (ez, y, -1, ψ_hxy) (ey, z, +1); hy: (ex, z, -1) (ez, x, +1, ψ_hyx);
@@ -86,9 +101,9 @@ __global__ void __launch_bounds__(BT) adj_h_kernel(Problem p, int par) {
                      (dh_x(L, HZ, P_HZX, -1.f, i) - dh_x(L, HZ, P_HZX, -1.f, i - 1));
     const float gz = -(dh_y(L, HX, P_HXY, -1.f, j) - dh_y(L, HX, P_HXY, -1.f, j - 1)) -
                      (dh_x(L, HY, P_HYX, 1.f, i) - dh_x(L, HY, P_HYX, 1.f, i - 1));
-    L.f(EX)[id] += gx;
-    L.f(EY)[id] += gy;
-    L.f(EZ)[id] += gz;
+    L.fn(EX)[id] = L.fo(EX)[id] + gx;
+    L.fn(EY)[id] = L.fo(EY)[id] + gy;
+    L.fn(EZ)[id] = L.fo(EZ)[id] + gz;
     // λ_ψ of the H memories at this cell
     const int xs = slab_index(i, p.nx, p.npml), ys = slab_index(j, p.ny, p.npml);
     if (xs >= 0) {
@@ -151,10 +166,11 @@ __device__ __forceinline__ float de_z(const Lam& L, int ec, float sign, int kk) 
     return sign * p.sz * L.v(ec, L.i, L.j, kk);
 }
 
-__global__ void __launch_bounds__(BT) adj_e_kernel(Problem p, int par) {
-    const int col = blockIdx.x * BT + threadIdx.x;
-    if (col >= p.nx * p.ny) return;
-    const Lam L{p, par, col % p.nx, col / p.nx, (int)blockIdx.y};
+__global__ void __launch_bounds__(BT) adj_e_kernel(Problem p, int par, Frame fr, long long ncols) {
+    int ci = 0, cj = 0;
+    const unsigned col = blockIdx.x * BT + threadIdx.x;
+    if (col >= (unsigned long long)ncols || !frame_column(fr, p.nx, p.ny, col, &ci, &cj)) return;
+    const Lam L{p, par, par ^ 1, ci, cj, (int)blockIdx.y};
     const int i = L.i, j = L.j, k = L.k;
     const size_t id = L.at(i, j, k);
     // E terms: ex: (hz, y, +1, ψ_exy) (hy, z, -1); ey: (hx, z, +1) (hz, x, -1, ψ_eyx);
@@ -165,9 +181,9 @@ __global__ void __launch_bounds__(BT) adj_e_kernel(Problem p, int par) {
                      (de_x(L, EZ, P_EZX, 1.f, i + 1) - de_x(L, EZ, P_EZX, 1.f, i));
     const float gz = -(de_y(L, EX, P_EXY, 1.f, j + 1) - de_y(L, EX, P_EXY, 1.f, j)) -
                      (de_x(L, EY, P_EYX, -1.f, i + 1) - de_x(L, EY, P_EYX, -1.f, i));
-    L.f(HX)[id] += gx;
-    L.f(HY)[id] += gy;
-    L.f(HZ)[id] += gz;
+    L.fn(HX)[id] = L.fo(HX)[id] + gx;
+    L.fn(HY)[id] = L.fo(HY)[id] + gy;
+    L.fn(HZ)[id] = L.fo(HZ)[id] + gz;
     const int xs = slab_index(i, p.nx, p.npml), ys = slab_index(j, p.ny, p.npml);
     if (xs >= 0) {
         const float b = cx_tab(p, T_EB)[i];
@@ -187,12 +203,12 @@ __global__ void __launch_bounds__(BT) adj_e_kernel(Problem p, int par) {
 
 // ∂L/∂E_y^{n+1} on the intensity plane: λ_Ey += coef · g · E_y (the
 // intensity is the window mean of E_y², g = ∂L/∂Ī).
-__global__ void __launch_bounds__(BT) adj_inject_kernel(Problem p, const float* g, const float* ey,
-                                                        float coef) {
+__global__ void __launch_bounds__(BT) adj_inject_kernel(Problem p, int par, const float* g,
+                                                        const float* ey, float coef) {
     const int col = blockIdx.x * BT + threadIdx.x;
     if (col >= p.nx * p.ny) return;
     const int i = col % p.nx, j = col / p.nx;
-    float* f = p.fbase[0] + EY * p.fstride;
+    const gptr<float> f = G(p.fbase[par]) + EY * p.fstride;
     f[((size_t)p.plane * p.ny + j) * p.pitch + i] += coef * g[col] * ey[col];
 }
 
@@ -203,7 +219,7 @@ __global__ void __launch_bounds__(BT) adj_inject_kernel(Problem p, const float* 
 // fixed butterfly order, so the result does not depend on scheduling. All
 // planes of a column are in flight at once (a thread per column would walk
 // them one after another).
-__global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, const int* slot_i,
+__global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, int par, const int* slot_i,
                                                       const int* slot_j, int nslots, int first,
                                                       float2 t, double2* G) {
     const int pair = blockIdx.x * (BT / 64) + (int)(threadIdx.x >> 6);
@@ -213,7 +229,7 @@ __global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, const int* slot
     const int i = slot_i[s], j = slot_j[s];
     // integer-plane components: E_x, E_y, H_z; half-plane: E_z, H_x, H_y
     const int half = (c == EZ || c == HX || c == HY) ? 1 : 0;
-    const float* f = p.fbase[0] + c * p.fstride + (size_t)j * p.pitch + i;
+    const float* f = p.fbase[par] + c * p.fstride + (size_t)j * p.pitch + i;
     const size_t plane = (size_t)p.ny * p.pitch;
     double re = 0.0, im = 0.0;
     for (int k = lane; k < p.nz; k += 64) {
@@ -234,31 +250,35 @@ __global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, const int* slot
 
 }  // namespace
 
-hipError_t launch_adjoint_h(const Problem& lam, int par, hipStream_t s) {
-    dim3 grid((unsigned)((lam.nx * lam.ny + BT - 1) / BT), lam.nz);
-    hipLaunchKernelGGL(adj_h_kernel, grid, dim3(BT), 0, s, lam, par);
+hipError_t launch_adjoint_h(const Problem& lam, int par, const Frame& fr, hipStream_t s) {
+    const long long nc = frame_columns(lam, fr);
+    if (nc == 0) return hipSuccess;
+    dim3 grid((unsigned)((nc + BT - 1) / BT), lam.nz);
+    hipLaunchKernelGGL(adj_h_kernel, grid, dim3(BT), 0, s, lam, par, fr, nc);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_e(const Problem& lam, int par, hipStream_t s) {
-    dim3 grid((unsigned)((lam.nx * lam.ny + BT - 1) / BT), lam.nz);
-    hipLaunchKernelGGL(adj_e_kernel, grid, dim3(BT), 0, s, lam, par);
+hipError_t launch_adjoint_e(const Problem& lam, int par, const Frame& fr, hipStream_t s) {
+    const long long nc = frame_columns(lam, fr);
+    if (nc == 0) return hipSuccess;
+    dim3 grid((unsigned)((nc + BT - 1) / BT), lam.nz);
+    hipLaunchKernelGGL(adj_e_kernel, grid, dim3(BT), 0, s, lam, par, fr, nc);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_inject(const Problem& lam, const float* g, const float* ey, float coef,
-                                 hipStream_t s) {
+hipError_t launch_adjoint_inject(const Problem& lam, int par, const float* g, const float* ey,
+                                 float coef, hipStream_t s) {
     hipLaunchKernelGGL(adj_inject_kernel, dim3((lam.nx * lam.ny + BT - 1) / BT), dim3(BT), 0, s,
-                       lam, g, ey, coef);
+                       lam, par, g, ey, coef);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_gacc(const Problem& lam, const int* slot_i, const int* slot_j,
+hipError_t launch_adjoint_gacc(const Problem& lam, int par, const int* slot_i, const int* slot_j,
                                int nslots, int first, float2 t, double2* G, hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const int waves = BT / 64;
     hipLaunchKernelGGL(adj_gacc_kernel, dim3((nslots * 3 + waves - 1) / waves), dim3(BT), 0, s,
-                       lam, slot_i, slot_j, nslots, first, t, G);
+                       lam, par, slot_i, slot_j, nslots, first, t, G);
     return hipGetLastError();
 }
 

@@ -67,6 +67,35 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// Column c of the frame -> (x, y). A plane holds fewer than 2^31 cells (the
+// context checks it), so the index math is 32-bit: unsigned divisions are a
+// fraction of the cost of 64-bit ones.
+__device__ __forceinline__ bool frame_column(const Frame& fr, int nx, int ny, unsigned c, int* x,
+                                             int* y) {
+    const unsigned unx = (unsigned)nx;
+    const unsigned nb = (unsigned)fr.y0 * unx;
+    const unsigned nt = (unsigned)(ny - fr.y1) * unx;
+    const unsigned nl = (unsigned)(fr.y1 - fr.y0) * (unsigned)fr.x0;
+    const unsigned nr = (unsigned)(fr.y1 - fr.y0) * (unsigned)(nx - fr.x1);
+    if (c < nb) {
+        *y = (int)(c / unx);
+        *x = (int)(c % unx);
+    } else if ((c -= nb) < nt) {
+        *y = fr.y1 + (int)(c / unx);
+        *x = (int)(c % unx);
+    } else if ((c -= nt) < nl) {
+        *y = fr.y0 + (int)(c / (unsigned)fr.x0);
+        *x = (int)(c % (unsigned)fr.x0);
+    } else if ((c -= nl) < nr) {
+        const unsigned wdt = (unsigned)(nx - fr.x1);
+        *y = fr.y0 + (int)(c / wdt);
+        *x = fr.x1 + (int)(c % wdt);
+    } else {
+        return false;
+    }
+    return true;
+}
+
 // Sum over a wave64 (deterministic butterfly order).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
