@@ -71,10 +71,13 @@ def test_dot_product_identity(bc, nsteps):
     s.close()
 
 
-def test_dot_product_identity_fused_grid():
-    """parity_mid grid: the forward step runs the fused interior kernel."""
+@pytest.mark.parametrize("bc", [L.BC_CPML, L.BC_PEC])
+def test_dot_product_identity_fused_grid(bc):
+    """parity_mid grid: the forward step runs the fused interior kernel, and
+    the transposed step runs it too (negated S) with the transposed-CPML
+    kernels on the frame around it."""
     w = W.parity_mid()
-    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, inject=False)
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, bc=bc, inject=False)
     adj = Adjoint(s)
     rng = np.random.default_rng(11)
     sh = _shapes(s)
@@ -94,6 +97,35 @@ def test_dot_product_identity_fused_grid():
     assert gap < 1e-5
     adj.close()
     s.close()
+
+
+@pytest.mark.parametrize("bc", [L.BC_CPML, L.BC_PEC])
+def test_transpose_decomposition_matches_whole_grid_kernels(bc):
+    """The transposed step on a fused-kernel context (interior kernel with
+    negated S + transposed-CPML kernels on the frame) against the
+    transposed-CPML kernels over the whole grid (split-kernel context), from
+    the same seeded λ, three steps."""
+    w = W.parity_mid()
+    sf = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, bc=bc, inject=False)
+    ss = GC.gpu_solver(w, kernel=L.KERNEL_SPLIT, bc=bc, inject=False)
+    af, as_ = Adjoint(sf), Adjoint(ss)
+    rng = np.random.default_rng(31)
+    sh = _shapes(sf)
+    for q, v in sh.items():
+        y = rng.standard_normal(v).astype(np.float32)
+        af.set_state(q, y)
+        as_.set_state(q, y)
+    af.transpose(3)
+    as_.transpose(3)
+    worst = 0.0
+    for q in sh:
+        a, b = af.get_state(q).astype(np.float64), as_.get_state(q).astype(np.float64)
+        rel = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        worst = max(worst, rel)
+    print(f"  fused-context vs whole-grid transpose: worst rel-L2 {worst:.1e}", flush=True)
+    assert worst < 1e-6
+    for x in (af, as_, sf, ss):
+        x.close()
 
 
 def _slab_to_full(arr, which, npml, nx, ny):
