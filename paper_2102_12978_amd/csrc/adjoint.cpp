@@ -19,8 +19,9 @@ hipError_t launch_adjoint_h(const Problem& lam, int par, const Frame& fr, hipStr
 hipError_t launch_adjoint_e(const Problem& lam, int par, const Frame& fr, hipStream_t s);
 hipError_t launch_adjoint_inject(const Problem& lam, int par, const float* g, const float* ey,
                                  float coef, hipStream_t s);
-hipError_t launch_adjoint_gacc(const Problem& lam, int par, const int* slot_i, const int* slot_j,
-                               int nslots, int first, float2 t, double2* G, hipStream_t s);
+hipError_t launch_adjoint_gacc(const Problem& lam, int par_h, int par_e, const int* slot_i,
+                               const int* slot_j, int nslots, float2 tH, float2 tE, double2* G,
+                               hipStream_t s);
 }  // namespace bfdtd
 
 struct fdtd_adjoint {
@@ -116,8 +117,9 @@ float2 time_value(const fdtd_ctx* c, double steps);
 // other's transposes), so the fused interior kernel runs it there; the
 // transposed-CPML kernels take the frame (the whole grid for the split
 // kernel choice or the periodic test mode). With correlations, G picks up
-// the H components of λ before the step and the E components after its
-// H-part transpose (they are final once λ_E of parity par ^ 1 is formed).
+// the H components of λ as they were before the step (parity par, left
+// intact) and the E components after its H-part transpose (final in
+// parity par ^ 1), in one launch after the step.
 void reverse_step(fdtd_adjoint* a, bool correlate, long long m) {
     fdtd_ctx* c = a->c;
     hipStream_t s = c->stream;
@@ -135,28 +137,16 @@ void reverse_step(fdtd_adjoint* a, bool correlate, long long m) {
             q.rec = nullptr;
             q.diag_mask = 0;
             q.plane = -1;
-            if (correlate)
-                check(launch_adjoint_gacc(a->lam, par, a->slot_i, a->slot_j, a->nslots, HX,
-                                          time_value(c, m + 1.5), a->G, s), "G (H)");
             check(launch_fused_interior(q, 0, par, c->rows, c->zchunk, c->xalign, nullptr, s,
                                         nullptr), "adjoint interior launch");
-            check(launch_adjoint_h(a->lam, par, fr, s), "adjoint H launch");
-            check(launch_adjoint_e(a->lam, par, fr, s), "adjoint E launch");
-            if (correlate)
-                check(launch_adjoint_gacc(a->lam, par ^ 1, a->slot_i, a->slot_j, a->nslots, EX,
-                                          time_value(c, m + 1.0), a->G, s), "G (E)");
-            a->lam_par ^= 1;
-            return;
         }
     }
-    if (correlate)
-        check(launch_adjoint_gacc(a->lam, par, a->slot_i, a->slot_j, a->nslots, HX,
-                                  time_value(c, m + 1.5), a->G, s), "G (H)");
     check(launch_adjoint_h(a->lam, par, fr, s), "adjoint H launch");
-    if (correlate)
-        check(launch_adjoint_gacc(a->lam, par ^ 1, a->slot_i, a->slot_j, a->nslots, EX,
-                                  time_value(c, m + 1.0), a->G, s), "G (E)");
     check(launch_adjoint_e(a->lam, par, fr, s), "adjoint E launch");
+    if (correlate)
+        check(launch_adjoint_gacc(a->lam, par, par ^ 1, a->slot_i, a->slot_j, a->nslots,
+                                  time_value(c, m + 1.5), time_value(c, m + 1.0), a->G, s),
+              "G");
     a->lam_par ^= 1;
 }
 

@@ -212,20 +212,26 @@ __global__ void __launch_bounds__(BT) adj_inject_kernel(Problem p, int par, cons
     f[((size_t)p.plane * p.ny + j) * p.pitch + i] += coef * g[col] * ey[col];
 }
 
-// G_c(slot) += T(t) Σ_k λ_c(k, j, i) e^{iβ z_c(k)} for one half step: three
-// components (first = EX or HX) of every antenna column, in double.
+// G_c(slot) += T(t) Σ_k λ_c(k, j, i) e^{iβ z_c(k)} for one step: the six
+// components of every antenna column, in double; the H components read λ
+// of parity par_h at the H time factor tH, the E components λ of parity
+// par_e at tE.
 // One wavefront per (antenna column, component): lane l sums the planes
 // k = l, l + 64, ... of that column, then the wavefront adds the lanes in a
 // fixed butterfly order, so the result does not depend on scheduling. All
 // planes of a column are in flight at once (a thread per column would walk
 // them one after another).
-__global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, int par, const int* slot_i,
-                                                      const int* slot_j, int nslots, int first,
-                                                      float2 t, double2* G) {
+__global__ void __launch_bounds__(BT) adj_gacc_kernel(Problem p, int par_h, int par_e,
+                                                      const int* slot_i, const int* slot_j,
+                                                      int nslots, float2 tH, float2 tE,
+                                                      double2* G) {
     const int pair = blockIdx.x * (BT / 64) + (int)(threadIdx.x >> 6);
-    if (pair >= nslots * 3) return;                      // whole wavefront
+    if (pair >= nslots * 6) return;                      // whole wavefront
     const int lane = threadIdx.x & 63;
-    const int s = pair / 3, c = first + pair % 3;
+    const int s = pair / 6, c = pair % 6;
+    const bool is_e = c <= EZ;
+    const int par = is_e ? par_e : par_h;
+    const float2 t = is_e ? tE : tH;
     const int i = slot_i[s], j = slot_j[s];
     // integer-plane components: E_x, E_y, H_z; half-plane: E_z, H_x, H_y
     const int half = (c == EZ || c == HX || c == HY) ? 1 : 0;
@@ -273,12 +279,13 @@ hipError_t launch_adjoint_inject(const Problem& lam, int par, const float* g, co
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_gacc(const Problem& lam, int par, const int* slot_i, const int* slot_j,
-                               int nslots, int first, float2 t, double2* G, hipStream_t s) {
+hipError_t launch_adjoint_gacc(const Problem& lam, int par_h, int par_e, const int* slot_i,
+                               const int* slot_j, int nslots, float2 tH, float2 tE, double2* G,
+                               hipStream_t s) {
     if (nslots <= 0) return hipSuccess;
     const int waves = BT / 64;
-    hipLaunchKernelGGL(adj_gacc_kernel, dim3((nslots * 3 + waves - 1) / waves), dim3(BT), 0, s,
-                       lam, par, slot_i, slot_j, nslots, first, t, G);
+    hipLaunchKernelGGL(adj_gacc_kernel, dim3((nslots * 6 + waves - 1) / waves), dim3(BT), 0, s,
+                       lam, par_h, par_e, slot_i, slot_j, nslots, tH, tE, G);
     return hipGetLastError();
 }
 
