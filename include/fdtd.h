@@ -276,7 +276,7 @@ int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchu
  * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
  * frames, and, when the grid has room for its interior and the device has
  * the free memory, the two-step kernel (fdtd_set_time_block) at rows {4, 2}
- * x z chunks {32, 16, 64, whole}. Each candidate is timed over at least
+ * x z chunks {nz/8, nz/16, nz/4, whole} (rounded up). Each candidate is timed over at least
  * steps_per_trial steps, and over more until the timed span reaches about
  * 2 ms. *best_rows / *best_zchunk (may be NULL)
  * receive the one-step kernel's tile; fdtd_get_info reports whether the

@@ -635,7 +635,9 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             const int keep_mask = (int)c->mask;
             c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
             c->time_block = 2;
-            std::vector<int> chunks2 = {32, 16, 64, 0};
+            // 8 or 16 chunks (each XCD then marches whole chunk layers of
+            // tiles), 4, and the whole z
+            std::vector<int> chunks2 = {(nz + 7) / 8, (nz + 15) / 16, (nz + 3) / 4, 0};
             for (int rows : {4, 2}) {
                 for (int cz : chunks2) {
                     if (cz > nz) continue;

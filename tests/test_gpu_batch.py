@@ -134,6 +134,9 @@ def test_instances_refuse_direct_stepping():
     assert lib.fdtd_reset(ctx) == L.ESTATE
     assert lib.fdtd_destroy(ctx) == L.ESTATE
     assert lib.fdtd_set_tile(ctx, 4, 0) == L.ESTATE
+    assert lib.fdtd_set_time_block(ctx, 2, 4, 0) == L.ESTATE
+    assert lib.fdtd_set_frame(ctx, L.FRAME_SPLIT, 32, 2) == L.ESTATE
+    assert lib.fdtd_autotune(ctx, 2, None, None) == L.ESTATE
     assert lib.fdtd_batch_instance(b._b, 2) is None
     assert lib.fdtd_batch_set_tile(b._b, 96, 0) == L.EINVAL
     assert lib.fdtd_batch_set_graph_steps(b._b, 3) == L.EINVAL
