@@ -276,11 +276,12 @@ int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchu
  * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
  * frames, and, when the grid has room for its interior and the device has
  * the free memory, the two-step kernel (fdtd_set_time_block) at rows {4, 2}
- * x z chunks {nz/8, nz/16, nz/4, whole} (rounded up). Each candidate is timed over at least
- * steps_per_trial steps, and over more until the timed span reaches about
- * 2 ms. *best_rows / *best_zchunk (may be NULL)
- * receive the one-step kernel's tile; fdtd_get_info reports whether the
- * two-step kernel won (time_block) and its tile. */
+ * x z chunks {nz/8, nz/16, nz/4, whole} (rounded up); trying it allocates
+ * the intermediate fields, which are freed again if it loses. Each
+ * candidate is timed over at least steps_per_trial steps, and over more
+ * until the timed span reaches about 2 ms. *best_rows / *best_zchunk (may
+ * be NULL) receive the one-step kernel's tile; fdtd_get_info reports
+ * whether the two-step kernel won (time_block) and its tile. */
 int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,
                   int32_t *best_zchunk);
 
@@ -345,8 +346,12 @@ typedef struct fdtd_adjoint_info {
 } fdtd_adjoint_info;
 
 /* Attach an adjoint to a forward context (which it borrows: destroy the
- * adjoint first). Allocates λ (fields, CPML memories) and one segment of
- * plane records. checkpoint_every >= 1. */
+ * adjoint first). Allocates λ (two parities of fields and CPML memories,
+ * like the forward state) and one segment of plane records.
+ * checkpoint_every >= 1. The transposed step follows the forward context's
+ * kernel choice: with the fused kernel its interior runs through the fused
+ * interior kernel (the forward step with negated Courant factors) and the
+ * transposed CPML kernels take the frame. */
 int fdtd_adjoint_create(fdtd_ctx *fwd, int32_t checkpoint_every, fdtd_adjoint **out);
 
 /* Free the adjoint's device memory. NULL-safe. */
@@ -432,7 +437,8 @@ const char *fdtd_batch_last_error(const fdtd_batch *b);
  * fdtd_get_info, fdtd_analytic_ey2), fdtd_set_state, fdtd_set_diagnostics
  * (window steps count from the batch's step 0), fdtd_set_injector and
  * fdtd_set_sector_weights work on it as on any context; fdtd_step,
- * fdtd_reset, fdtd_set_tile, fdtd_autotune and fdtd_destroy return
+ * fdtd_reset, fdtd_set_tile, fdtd_set_frame, fdtd_set_time_block,
+ * fdtd_autotune and fdtd_destroy return
  * FDTD_ESTATE. The energy diagnostic is not computed for batch instances. */
 fdtd_ctx *fdtd_batch_instance(fdtd_batch *b, int32_t q);
 
