@@ -86,7 +86,7 @@ def batch_measure(torch, stream, steps=1000, warmup=20):
     from paper_2102_12978_amd import analysis as A
     from paper_2102_12978_amd import workloads as W
     from paper_2102_12978_amd.batch import Batch
-    ws = W.config3_instances()
+    ws = W.batch64_instances()
     b = Batch(ws, stream=stream.cuda_stream)
     cols, zc = b.autotune(3)
     b.set_graph_steps(20)
@@ -170,8 +170,8 @@ def adjoint_measure(torch, stream):
     from paper_2102_12978_amd import _lib as L
     from paper_2102_12978_amd import workloads as W
     from paper_2102_12978_amd.adjoint import SectorSensitivity, central_lobe_target, on_axis
-    w = W.config4()
-    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    w = W.grad192()
+    amp, ph = W.sector_params(seed=2, sectors=256)
     sens = SectorSensitivity(w, stream=stream.cuda_stream)
     s = sens.solver
     s.autotune(3)        # the tile and steps per pass used by both timings
@@ -236,8 +236,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver has "
-              "no multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
+              "steps one domain on one GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -249,7 +249,7 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    w = W.config2()
+    w = W.grid768()
     s = Solver.from_workload(w, kernel=L.KERNEL_FUSED, stream=stream.cuda_stream)
     s.set_workload_injector(w)
     cells = s.nx * s.ny * s.nz

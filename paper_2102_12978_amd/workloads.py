@@ -87,24 +87,24 @@ class Workload:
         return int(round(self.window_periods * self.steps_per_period))
 
 
-def config0():
+def cube32():
     """32×32×32, Δx = λ/16, θ = 10°, m = 0, annulus 12Δx × 2Δx, 8-cell CPML, 200 steps."""
-    return Workload("c0_32cube_theta10_m0", 32, 32, 32, 16.0, 10.0, 0, 12.0, 2.0, 8, 200)
+    return Workload("cube32_theta10_m0", 32, 32, 32, 16.0, 10.0, 0, 12.0, 2.0, 8, 200)
 
 
-def config1(order=0):
+def grid256(order=0):
     """256×256×64 (z fitted), Δx = λ/20, θ = 15°, m = 0 or 1, annulus 100Δx, 2000 steps."""
-    return Workload(f"c1_256x256x64_theta15_m{order}", 256, 256, 64, 20.0, 15.0, order,
+    return Workload(f"grid256x256x64_theta15_m{order}", 256, 256, 64, 20.0, 15.0, order,
                     100.0, 2.0, 16, 2000)
 
 
-def config2():
+def grid768():
     """768×768×256 (z fitted to 255), Δx = λ/24, θ = 20°, m = 2, annulus 320Δx, 1000 steps."""
-    return Workload("c2_768x768x256_theta20_m2", 768, 768, 256, 24.0, 20.0, 2, 320.0, 2.0,
+    return Workload("grid768x768x256_theta20_m2", 768, 768, 256, 24.0, 20.0, 2, 320.0, 2.0,
                     16, 1000)
 
 
-def config3_instances(seed=1, count=64):
+def batch64_instances(seed=1, count=64):
     """64 uneven instances: nx = ny ~ U{64..160}, nz_hint ~ U{48..64},
     θ ~ {5,10,15,20,25,30}°, m ~ U{0..3}; 8-cell CPML, R_B = 0.8 (nx/2 - 8) Δx."""
     rng = np.random.default_rng(seed)
@@ -114,14 +114,14 @@ def config3_instances(seed=1, count=64):
         nzh = int(rng.integers(48, 65))
         th = float(rng.choice([5.0, 10.0, 15.0, 20.0, 25.0, 30.0]))
         m = int(rng.integers(0, 4))
-        out.append(Workload(f"c3_inst{q:02d}", nx, nx, nzh, 20.0, th, m,
+        out.append(Workload(f"batch64_inst{q:02d}", nx, nx, nzh, 20.0, th, m,
                             0.8 * (nx / 2 - 8), 2.0, 8, 1000))
     return out
 
 
 def batch_small(seed=3, count=5):
-    """Small uneven instances for batch parity (the config-3 recipe scaled
-    down): nx = ny ~ U{40..72}, nz_hint ~ U{12..20}, θ ~ {10,15,20,25,30}°,
+    """Small uneven instances for batch parity (the 64-instance batch recipe
+    scaled down): nx = ny ~ U{40..72}, nz_hint ~ U{12..20}, θ ~ {10,15,20,25,30}°,
     m ~ U{0..3}; Δx = λ/16, 8-cell CPML, R_B = 0.8 (nx/2 - 8) Δx, 2-period
     ramp, 45 steps."""
     rng = np.random.default_rng(seed)
@@ -136,24 +136,24 @@ def batch_small(seed=3, count=5):
     return out
 
 
-def config4():
+def grad192():
     """192×192×64 (z fitted), Δx = λ/20, θ = 12°, m = 0, annulus 64Δx, 1500 steps,
     checkpoints every 100 steps, 256 sector weights, 10-period ramp."""
-    return Workload("c4_192x192x64_theta12_m0", 192, 192, 64, 20.0, 12.0, 0, 64.0, 2.0,
+    return Workload("grad192x192x64_theta12_m0", 192, 192, 64, 20.0, 12.0, 0, 64.0, 2.0,
                     16, 1500, ramp_periods=10.0,
                     extra={"checkpoint_every": 100, "sectors": 256})
 
 
-def config4_tiny():
-    """24×24×(24 hint) copy of config 4 for the autograd reference: Δx = λ/20,
+def grad24():
+    """24×24×(24 hint) copy of the 192² gradient workload for the autograd reference: Δx = λ/20,
     θ = 12°, m = 0, 4-cell CPML, R_B = 0.8 (12 - 4) Δx, δs = 2Δx, 300 steps,
     2.5-period ramp, window = last 5 periods, the same 256 seed-2 sector
     weights."""
-    return Workload("c4tiny_24_theta12_m0", 24, 24, 24, 20.0, 12.0, 0, 6.4, 2.0, 4, 300,
+    return Workload("grad24_theta12_m0", 24, 24, 24, 20.0, 12.0, 0, 6.4, 2.0, 4, 300,
                     ramp_periods=2.5, extra={"checkpoint_every": 100, "sectors": 256})
 
 
-def config4_sector_params(seed=2, sectors=256):
+def sector_params(seed=2, sectors=256):
     """Initial sector amplitudes a = 1 + 0.05 N(0,1) and phases φ = 0.1 N(0,1)
     (amplitudes drawn first)."""
     rng = np.random.default_rng(seed)
@@ -162,7 +162,7 @@ def config4_sector_params(seed=2, sectors=256):
     return amp, phase
 
 
-def config4_fd_sectors():
+def fd_probe_sectors():
     """The 16 finite-difference probes: amplitude and phase of sectors 32q + 5."""
     return [32 * q + 5 for q in range(8)]
 

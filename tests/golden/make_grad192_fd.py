@@ -1,4 +1,4 @@
-"""Writes c4_fd_gradient.json: central finite differences (h = 1e-3) of the
+"""Writes grad192_fd_gradient.json: central finite differences (h = 1e-3) of the
 192×192×61 intensity loss with respect to 8 sector amplitudes and 8 sector
 phases, computed with the FP64 oracle only.
 
@@ -16,7 +16,7 @@ oracle runs with only that sector switched on (weight 1 and weight i);
 every perturbed loss L(p ± h) is then evaluated in full from its planes and
 differenced centrally. 18 oracle runs of 1500 steps in all.
 
-    python tests/golden/make_c4_fd.py [--procs 5]
+    python tests/golden/make_grad192_fd.py [--procs 5]
 """
 import argparse
 import json
@@ -37,11 +37,11 @@ from oracle import yee as Y             # noqa: E402
 from paper_2102_12978_amd import workloads as W   # noqa: E402
 
 H = 1e-3
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c4_fd_gradient.json")
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grad192_fd_gradient.json")
 
 
 def setup():
-    w = W.config4()
+    w = W.grad192()
     nz, dz = P.fit_periodic_z(W.WAVELENGTH, w.theta, w.dx, w.nz_hint)
     g = P.Grid(w.nx, w.ny, nz, w.dx, w.dx, dz, w.courant, P.BC_CPML, w.npml, w.grade,
                w.sigma_scale, w.kappa_max, w.alpha_max)
@@ -67,8 +67,8 @@ def main():
     a = ap.parse_args()
     w, g = setup()
     nsec = w.extra["sectors"]
-    amp0, ph0 = W.config4_sector_params(seed=2, sectors=nsec)
-    sectors = W.config4_fd_sectors()
+    amp0, ph0 = W.sector_params(seed=2, sectors=nsec)
+    sectors = W.fd_probe_sectors()
     jobs = [(np.ones(nsec), np.zeros(nsec)), (amp0, ph0)]
     for s in sectors:
         only = np.zeros(nsec)
@@ -107,9 +107,9 @@ def main():
         fd_a.append((loss(moved(H, 0.0)) - loss(moved(-H, 0.0))) / (2 * H))
         fd_p.append((loss(moved(0.0, H)) - loss(moved(0.0, -H))) / (2 * H))
     out = {
-        "_recipe": "Central differences, h = 1e-3, of the config-4 intensity loss; FP64 "
+        "_recipe": "Central differences, h = 1e-3, of the 192² gradient workload's intensity loss; FP64 "
                    "oracle runs combined by linearity in the source weights. Written by "
-                   "tests/golden/make_c4_fd.py (oracle only).",
+                   "tests/golden/make_grad192_fd.py (oracle only).",
         "h": H, "sectors": sectors, "A_on_axis": float(A), "loss": loss(base),
         "grad_amp_fd": fd_a, "grad_phase_fd": fd_p,
         "grid": [g.nx, g.ny, g.nz], "steps": w.steps, "window_steps": w.window_steps,

@@ -230,7 +230,7 @@ def test_autograd_function():
     sens.close()
 
 
-def _c4_loss_grad(sens, amp, ph, A):
+def _grad192_loss_grad(sens, amp, ph, A):
     from paper_2102_12978_amd.adjoint import central_lobe_target
     region, j0sq = central_lobe_target(sens)
     a = torch.tensor(amp, requires_grad=True)
@@ -248,12 +248,12 @@ def test_torch_reference_24():
     through the pure-PyTorch FP64 forward."""
     from oracle import torch_ref as T
     from paper_2102_12978_amd.adjoint import on_axis
-    w = W.config4_tiny()
-    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    w = W.grad24()
+    amp, ph = W.sector_params(seed=2, sectors=256)
     sens = SectorSensitivity(w)
     print(f"[gpu case] {w.name}: {sens.steps} steps, window from {sens.window_begin}", flush=True)
     A = on_axis(sens.intensity(np.ones(256), np.zeros(256)).astype(np.float64))
-    loss, ga, gp, region, j0sq = _c4_loss_grad(sens, amp, ph, A)
+    loss, ga, gp, region, j0sq = _grad192_loss_grad(sens, amp, ph, A)
     g = cases.oracle_grid(w)
     ref = T.TorchYee(g, cases.oracle_injector(w, amp=amp, phase=ph))
     a2 = torch.tensor(amp, requires_grad=True)
@@ -271,19 +271,19 @@ def test_torch_reference_24():
     sens.close()
 
 
-def test_c4_gradient_vs_finite_differences():
+def test_grad192_gradient_vs_finite_differences():
     """192×192×61, 1500 steps, checkpoints every 100: adjoint gradients at 8
     amplitudes and 8 phases (sectors 32 q + 5) against FP64 central
-    differences (h = 1e-3) stored by tests/golden/make_c4_fd.py."""
+    differences (h = 1e-3) stored by tests/golden/make_grad192_fd.py."""
     import json
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "c4_fd_gradient.json")
+    path = os.path.join(os.path.dirname(__file__), "golden", "grad192_fd_gradient.json")
     fd = json.load(open(path))
-    w = W.config4()
-    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    w = W.grad192()
+    amp, ph = W.sector_params(seed=2, sectors=256)
     sens = SectorSensitivity(w)
     print(f"[gpu case] {w.name}: {sens.steps} steps, checkpoints every {sens.every}", flush=True)
-    loss, ga, gp, _, _ = _c4_loss_grad(sens, amp, ph, fd["A_on_axis"])
+    loss, ga, gp, _, _ = _grad192_loss_grad(sens, amp, ph, fd["A_on_axis"])
     inf = sens.adj.info()
     assert inf.checkpoints == 15 and inf.recompute_steps == 200
     sec = fd["sectors"]

@@ -55,11 +55,11 @@ def test_validation_band(m):
 
 @pytest.mark.parametrize("m", [0, 1])
 def test_report_256_grid(m):
-    res, ey2, _ = _run(W.config1(m))
+    res, ey2, _ = _run(W.grid256(m))
     assert np.isfinite(ey2).all() and res["alpha"] > 0
 
 
 def test_report_large_grid_long_run():
-    w = W.config2()
+    w = W.grid768()
     res, ey2, _ = _run(w, steps=3200, window=5 * 48)
     assert np.isfinite(ey2).all() and res["alpha"] > 0

@@ -143,16 +143,16 @@ def test_instances_refuse_direct_stepping():
     b.close()
 
 
-def test_config3_batch_sampled_instances():
+def test_batch64_sampled_instances():
     """The 64 seed-1 instances (48.5 M cells) in the benchmark's launch
     configuration (autotuned shape, 20-step graphs); instances 0, 21 and 63
     must equal their single split runs bit for bit after 24 steps."""
-    ws = W.config3_instances()
+    ws = W.batch64_instances()
     b = Batch(ws)
     cols, zc = b.autotune(1)
     b.set_graph_steps(20)
     inf = b.info()
-    print(f"  c3: {inf.count} instances, {inf.cells / 1e6:.2f} M cells, kernel={inf.kernel} "
+    print(f"  batch: {inf.count} instances, {inf.cells / 1e6:.2f} M cells, kernel={inf.kernel} "
           f"cols={cols} zchunk={zc}, "
           f"{inf.work_items} work items, {inf.blocks} workgroups", flush=True)
     assert inf.count == 64 and inf.cells == 48_492_676   # sum of nx ny nz after the z fits

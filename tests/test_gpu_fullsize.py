@@ -30,7 +30,7 @@ COLUMNS = [(95, 100), (96, 101), (32, 17), (31, 16), (735, 748), (736, 749), (40
 
 
 def test_large_grid_sampled_columns():
-    w = W.config2()
+    w = W.grid768()
     steps = 3
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=16)
     g = cases.oracle_grid(w)

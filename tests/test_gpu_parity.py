@@ -40,9 +40,9 @@ def _compare(s, st, g, psi=True):
 
 
 @pytest.mark.parametrize("kernel", [L.KERNEL_SPLIT, L.KERNEL_FUSED])
-def test_config0_forward(kernel):
+def test_cube32_forward(kernel):
     """32³, Δx = λ/16, θ = 10°, m = 0, annulus 12Δx, 8-cell CPML, 200 steps."""
-    w = W.config0()
+    w = W.cube32()
     s = GC.gpu_solver(w, kernel=kernel)
     s.step(w.steps)
     g, st = GC.oracle_run(w, w.steps)
@@ -117,9 +117,9 @@ def test_ragged_small_grid():
 @pytest.mark.parametrize("bc", [P.BC_PERIODIC, P.BC_PEC])
 @pytest.mark.parametrize("kernel", [L.KERNEL_SPLIT, L.KERNEL_FUSED])
 def test_random_start_no_source(bc, kernel):
-    """Seed-0 U(-1,1) fields, no source: periodic box (config 0 random run)
+    """Seed-0 U(-1,1) fields, no source: periodic box (the 32³ random run)
     and PEC walls. Checks the fields, the energy invariant and div H."""
-    w = W.config0()
+    w = W.cube32()
     g, st0 = GC.random_start(w, bc)
     s = GC.gpu_solver(w, kernel=kernel, bc=bc, inject=False)
     for i, c in enumerate(GC.COMPS):
@@ -294,13 +294,13 @@ def test_fused_frame(xalign, rows, zchunk, frows):
     r.close()
 
 
-@pytest.mark.parametrize("maker", [W.config0, W.parity_small, W.parity_gauss])
+@pytest.mark.parametrize("maker", [W.cube32, W.parity_small, W.parity_gauss])
 def test_fused_frame_small_grids(maker):
     """Grids with no interior or a small one: the fused frame covers the
     whole grid or a ragged ring (PEC walls, CPML corners, lanes past nx)."""
     w = maker()
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
-    s.set_frame(L.FRAME_FUSED, 64, 4 if maker is W.config0 else 2)
+    s.set_frame(L.FRAME_FUSED, 64, 4 if maker is W.cube32 else 2)
     s.step(w.steps)
     g, st = GC.oracle_run(w, w.steps)
     _compare(s, st, g)

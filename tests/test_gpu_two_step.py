@@ -77,7 +77,7 @@ def test_bit_identical_with_source(rows, zchunk, steps):
 
 
 @pytest.mark.parametrize("maker,rows,zchunk", [(W.parity_wide, 4, 5), (W.parity_wide, 2, 0),
-                                               (W.config4, 4, 16), (W.parity_gauss, 2, 3)])
+                                               (W.grad192, 4, 16), (W.parity_gauss, 2, 3)])
 def test_bit_identical_random_start(maker, rows, zchunk):
     w = maker()
     one, two = _solvers(w, rows, zchunk)
@@ -159,7 +159,7 @@ def test_fallbacks():
     _assert_identical(one, two, w, "energy on")
     one.close()
     two.close()
-    w0 = W.config0()
+    w0 = W.cube32()
     w0.steps = 12
     one, two = _solvers(w0, 4, 0)
     assert two.info().interior_cells == 0 or two.info().time_block == 2
@@ -194,7 +194,7 @@ def test_benchmark_grid_bit_identical():
     """768x768x255 (the benchmark grid): random fields and CPML memories,
     antenna on, four steps with the two-step kernel (4 rows, z chunks of 32)
     against four one-step launches."""
-    w = W.config2()
+    w = W.grid768()
     one, two = _solvers(w, 4, 32)
     print(f"  {w.name}: random state", flush=True)
     _random_start((one, two), w, seed=23)

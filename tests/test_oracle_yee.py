@@ -128,12 +128,12 @@ def test_divergence_invariants():
 def test_z_fit_hand_cases():
     """§4 periodic z: whole axial periods; values worked out by hand."""
     lam = 800e-9
-    # c0: λ_z = 16/cos10° = 16.2469 cells, p = round(32/16.2469) = 2, nz = round(32.494) = 32
+    # 32³ grid: λ_z = 16/cos10° = 16.2469 cells, p = round(32/16.2469) = 2, nz = round(32.494) = 32
     nz, dz = P.fit_periodic_z(lam, math.radians(10), lam / 16, 32)
     assert nz == 32 and abs(dz / (lam / 16) - 2 * 16 / math.cos(math.radians(10)) / 32) < 1e-14
-    # c1: λ_z = 20.7055, p = 3, nz = round(62.116) = 62
+    # 256² grid: λ_z = 20.7055, p = 3, nz = round(62.116) = 62
     assert P.fit_periodic_z(lam, math.radians(15), lam / 20, 64)[0] == 62
-    # c2: λ_z = 25.5404, p = 10, nz = round(255.40) = 255
+    # 768² grid: λ_z = 25.5404, p = 10, nz = round(255.40) = 255
     assert P.fit_periodic_z(lam, math.radians(20), lam / 24, 256)[0] == 255
     # tiny hint never gives zero periods
     assert P.fit_periodic_z(lam, math.radians(30), lam / 16, 1)[0] == 18

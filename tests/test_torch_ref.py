@@ -15,9 +15,9 @@ from tests import cases
 
 
 def _tiny():
-    w = W.config4_tiny()
+    w = W.grad24()
     g = cases.oracle_grid(w)
-    amp, ph = W.config4_sector_params(seed=2, sectors=256)
+    amp, ph = W.sector_params(seed=2, sectors=256)
     return w, g, amp, ph
 
 
