@@ -29,8 +29,8 @@ struct fdtd_adjoint {
     int every = 100;                    // checkpoint interval (steps)
     Problem lam{};                      // λ: fields and ψ ping-pong, like the forward state
     int lam_par = 0;                    // parity of the current λ
-    std::vector<void*> allocs;
-    long long device_bytes = 0;
+    std::vector<std::pair<void*, size_t>> allocs;   // device buffers and their bytes
+    long long device_bytes = 0;                      // sum of the bytes in allocs
     // checkpoints of the forward state after s * every steps
     std::vector<float*> ck_f, ck_psi;
     std::vector<int> ck_par;
@@ -72,15 +72,19 @@ template <typename T>
 T* aalloc(fdtd_adjoint* a, size_t count) {
     void* p = nullptr;
     check(hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)), "hipMalloc");
-    a->allocs.push_back(p);
+    a->allocs.emplace_back(p, std::max<size_t>(1, count) * sizeof(T));
     a->device_bytes += (long long)(std::max<size_t>(1, count) * sizeof(T));
     return static_cast<T*>(p);
 }
 
 void afree(fdtd_adjoint* a, void* p) {
     if (!p) return;
-    auto it = std::find(a->allocs.begin(), a->allocs.end(), p);
-    if (it != a->allocs.end()) a->allocs.erase(it);
+    auto it = std::find_if(a->allocs.begin(), a->allocs.end(),
+                           [p](const std::pair<void*, size_t>& q) { return q.first == p; });
+    if (it != a->allocs.end()) {
+        a->device_bytes -= (long long)it->second;
+        a->allocs.erase(it);
+    }
     (void)hipFree(p);
 }
 
@@ -312,7 +316,7 @@ int fdtd_adjoint_create(fdtd_ctx* fwd, int32_t checkpoint_every, fdtd_adjoint** 
 int fdtd_adjoint_destroy(fdtd_adjoint* a) {
     if (!a) return FDTD_OK;
     if (a->c) (void)hipStreamSynchronize(a->c->stream);
-    for (void* p : a->allocs) (void)hipFree(p);
+    for (const auto& q : a->allocs) (void)hipFree(q.first);
     delete a;
     return FDTD_OK;
 }

@@ -168,7 +168,7 @@ int fdtd_destroy(fdtd_ctx* ctx) {
     }
     if (!ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
     delete ctx->timer;
-    for (void* ptr : ctx->allocs) (void)hipFree(ptr);
+    for (const auto& a : ctx->allocs) (void)hipFree(a.first);
     delete ctx;
     return FDTD_OK;
 }
@@ -496,7 +496,6 @@ int fdtd_set_time_block(fdtd_ctx* c, int32_t steps, int32_t rows, int32_t zchunk
         if (steps == 1 && c->mid) {
             check(hipStreamSynchronize(c->stream), "sync");
             dfree(c, c->mid);
-            c->device_bytes -= (long long)(6 * (size_t)c->p.fstride * sizeof(float));
             c->mid = nullptr;
         }
         c->time_block = steps;
@@ -552,9 +551,47 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                     chunks.push_back(dz);
             }
         }
-        hipEvent_t e0, e1;
-        check(hipEventCreate(&e0), "event");
-        check(hipEventCreate(&e1), "event");
+        // Whatever way the tuning ends, the profiler the trials detach comes
+        // back and the events go; if it ends with an error part-way, the
+        // settings and the energy mask the trials replaced are put back and
+        // an intermediate buffer this call allocated is freed.
+        struct Restore {
+            fdtd_ctx* c;
+            int rows, zchunk, frame, xalign, frame_rows, time_block, tb_rows, tb_zchunk;
+            unsigned mask;
+            EventTimer* timer;
+            bool had_mid;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            bool done = false;
+            ~Restore() {
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+                c->timer = timer;
+                if (done) return;
+                c->rows = rows;
+                c->zchunk = zchunk;
+                c->frame = frame;
+                c->xalign = xalign;
+                c->frame_rows = frame_rows;
+                c->time_block = time_block;
+                c->tb_rows = tb_rows;
+                c->tb_zchunk = tb_zchunk;
+                c->mask = mask;
+                (void)hipStreamSynchronize(c->stream);
+                if (c->mid && !had_mid) {
+                    dfree(c, c->mid);
+                    c->mid = nullptr;
+                }
+                try {
+                    ensure_partials(c);
+                } catch (...) {
+                }
+            }
+        } rs{c, c->rows, c->zchunk, c->frame, c->xalign, c->frame_rows, c->time_block,
+             c->tb_rows, c->tb_zchunk, c->mask, c->timer, c->mid != nullptr};
+        check(hipEventCreate(&rs.e0), "event");
+        check(hipEventCreate(&rs.e1), "event");
+        const hipEvent_t e0 = rs.e0, e1 = rs.e1;
         // Milliseconds per step of `launch(steps)` (each call advancing
         // `per_call` steps): one untimed call, then at least steps_per_trial
         // steps, repeated with more steps until the timed span reaches 2 ms
@@ -584,7 +621,6 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         };
         float best = 1e30f;
         int br = c->rows, bz = c->zchunk, bf = c->frame, ba = c->xalign, bfr = c->frame_rows;
-        LaunchTimer* keep_timer = c->timer;
         c->timer = nullptr;
         const int frames[5][3] = {{FDTD_FRAME_SPLIT, 32, 2}, {FDTD_FRAME_FUSED, 32, 2},
                                   {FDTD_FRAME_FUSED, 64, 2}, {FDTD_FRAME_FUSED, 32, 4},
@@ -622,7 +658,7 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         // for its interior and the device for the intermediate fields
         const size_t mid_bytes = 6 * (size_t)c->p.fstride * sizeof(float);
         size_t free_b = 0, total_b = 0;
-        const bool had_mid = c->mid != nullptr;
+        const bool had_mid = rs.had_mid;
         bool try2 = !c->p.periodic && fused2_interior_rect(c->p, 4).x1 > 0;
         if (try2 && !had_mid) {
             try2 = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
@@ -631,8 +667,6 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         }
         int bt = 1, btr = c->tb_rows, btz = c->tb_zchunk;
         if (try2) {
-            const int keep_tb = c->time_block, keep_r = c->tb_rows, keep_z = c->tb_zchunk;
-            const int keep_mask = (int)c->mask;
             c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
             c->time_block = 2;
             // 8 or 16 chunks (each XCD then marches whole chunk layers of
@@ -652,14 +686,11 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                     }
                 }
             }
-            c->mask = (unsigned)keep_mask;
-            c->time_block = keep_tb;
-            c->tb_rows = keep_r;
-            c->tb_zchunk = keep_z;
+            c->mask = rs.mask;
+            c->time_block = rs.time_block;
+            c->tb_rows = rs.tb_rows;
+            c->tb_zchunk = rs.tb_zchunk;
         }
-        c->timer = static_cast<EventTimer*>(keep_timer);
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         if (bt == 2) {
             c->time_block = 2;
             c->tb_rows = btr;
@@ -669,10 +700,10 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             if (c->mid && !had_mid) {
                 check(hipStreamSynchronize(c->stream), "sync");
                 dfree(c, c->mid);
-                c->device_bytes -= (long long)mid_bytes;
                 c->mid = nullptr;
             }
         }
+        rs.done = true;
         if (best_rows) *best_rows = br;
         if (best_zchunk) *best_zchunk = bz;
     });

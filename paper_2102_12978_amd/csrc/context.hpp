@@ -73,8 +73,8 @@ struct fdtd_ctx {
     int device = 0;
     double ry = 1, rz = 1;
     bfdtd::Problem p{};
-    std::vector<void*> allocs;
-    long long device_bytes = 0;
+    std::vector<std::pair<void*, size_t>> allocs;   // device buffers and their bytes
+    long long device_bytes = 0;                      // sum of the bytes in allocs
     // antenna
     bool has_inj = false;
     bfdtd::Antenna ant;
@@ -135,7 +135,7 @@ T* dalloc(fdtd_ctx* c, size_t count) {
     if (count == 0) return nullptr;
     void* ptr = nullptr;
     check(hipMalloc(&ptr, count * sizeof(T)), "hipMalloc");
-    c->allocs.push_back(ptr);
+    c->allocs.emplace_back(ptr, count * sizeof(T));
     c->device_bytes += (long long)(count * sizeof(T));
     check(hipMemsetAsync(ptr, 0, count * sizeof(T), c->stream), "hipMemsetAsync");
     return static_cast<T*>(ptr);
@@ -143,8 +143,12 @@ T* dalloc(fdtd_ctx* c, size_t count) {
 
 inline void dfree(fdtd_ctx* c, void* ptr) {
     if (!ptr) return;
-    auto it = std::find(c->allocs.begin(), c->allocs.end(), ptr);
-    if (it != c->allocs.end()) c->allocs.erase(it);
+    auto it = std::find_if(c->allocs.begin(), c->allocs.end(),
+                           [ptr](const std::pair<void*, size_t>& a) { return a.first == ptr; });
+    if (it != c->allocs.end()) {
+        c->device_bytes -= (long long)it->second;
+        c->allocs.erase(it);
+    }
     (void)hipFree(ptr);
 }
 

@@ -203,3 +203,50 @@ def test_benchmark_grid_bit_identical():
     _assert_identical(one, two, w, "768 grid")
     one.close()
     two.close()
+
+
+def test_device_bytes_accounting():
+    """The intermediate buffer's bytes are counted while it exists and
+    subtracted when it is freed: by fdtd_set_time_block(1, ...) and by an
+    autotune call whose two-step trials lose. Regrown time tables replace
+    their old bytes, not add to them. The profiler stays attached across
+    autotune."""
+    w = W.parity_mid()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    s.step(2)
+    b0 = s.info().device_bytes
+    s.set_time_block(2, 4, 0)
+    b2 = s.info().device_bytes
+    mid = b2 - b0
+    assert mid > 0
+    for _ in range(3):
+        s.set_time_block(1, 4, 0)
+        assert s.info().device_bytes == b0
+        s.set_time_block(2, 2, 0)
+        assert s.info().device_bytes == b2
+    s.set_time_block(1, 4, 0)
+    s.profile(True)
+    s.autotune(2)
+    inf = s.info()
+    # the intermediate buffer stays only if the two-step path won; the fused
+    # frame trials may have grown the tile list and partial-sum buffers,
+    # which are kept (a few tens of kB here)
+    extra = inf.device_bytes - b0 - (mid if inf.time_block == 2 else 0)
+    print(f"  autotune: time_block {inf.time_block}, {extra} B of trial buffers kept", flush=True)
+    assert 0 <= extra < mid // 10
+    # the trials run untimed and the profiler is back afterwards
+    s.step(2)
+    prof = s.profile_read()
+    assert sum(v[0] for v in prof.values()) > 0
+    s.profile(False)
+    # past the time tables' first capacity, twice: the E and H tables (two
+    # complex floats, 16 B per step) grow at most to twice the steps asked
+    # for, and only the last size counts
+    before = s.info().device_bytes
+    s.step(1200)
+    s.step(1200)
+    upto = s.info().step
+    grown = s.info().device_bytes - before
+    print(f"  mid buffer {mid} B; time tables grew by {grown} B up to step {upto}", flush=True)
+    assert 0 < grown <= 16 * 2 * upto
+    s.close()
