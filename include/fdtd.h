@@ -279,7 +279,11 @@ int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchu
  * x z chunks {nz/8, nz/16, nz/4, whole} (rounded up); trying it allocates
  * the intermediate fields, which are freed again if it loses. Each
  * candidate is timed over at least steps_per_trial steps, and over more
- * until the timed span reaches about 2 ms. *best_rows / *best_zchunk (may
+ * until the timed span reaches about 2 ms. One-step trials read what the
+ * previous trial wrote, as a run does: they go back and forth between the
+ * free parity and a scratch set of fields and CPML memories that this call
+ * allocates and frees (when the device lacks the memory, each trial re-runs
+ * the same step from the live state instead). *best_rows / *best_zchunk (may
  * be NULL) receive the one-step kernel's tile; fdtd_get_info reports
  * whether the two-step kernel won (time_block) and its tile. */
 int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,

@@ -242,16 +242,27 @@ def test_state_roundtrip_and_reset():
 
 
 def test_autotune_leaves_state_alone():
+    """Autotune between steps 20 and 21: the run then matches the oracle, and
+    an untuned run bit for bit (every tile, frame and time-block choice gives
+    the same bits), fields and CPML memories."""
     w = W.parity_mid()
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    r = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
     s.step(20)
     rows, zc = s.autotune(2)
-    print(f"  autotune picked rows={rows} zchunk={zc}", flush=True)
+    inf = s.info()
+    print(f"  autotune picked rows={rows} zchunk={zc} time_block={inf.time_block} "
+          f"tb_rows={inf.tb_rows} tb_zchunk={inf.tb_zchunk}", flush=True)
     assert rows in (4, 8)
     s.step(w.steps - 20)
+    r.step(w.steps)
+    for q in list(range(6)) + (list(GC.PSI) if s.npml > 0 else []):
+        a, b = s.get_state(q), r.get_state(q)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"array {q}"
     g, st = GC.oracle_run(w, w.steps)
     _compare(s, st, g)
     s.close()
+    r.close()
 
 
 def test_source_linearity_on_gpu():
