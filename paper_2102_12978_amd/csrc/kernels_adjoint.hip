@@ -101,22 +101,35 @@ __global__ void __launch_bounds__(BT) adj_h_kernel(Problem p, int par, Frame fr,
                      (dh_x(L, HZ, P_HZX, -1.f, i) - dh_x(L, HZ, P_HZX, -1.f, i - 1));
     const float gz = -(dh_y(L, HX, P_HXY, -1.f, j) - dh_y(L, HX, P_HXY, -1.f, j - 1)) -
                      (dh_x(L, HY, P_HYX, 1.f, i) - dh_x(L, HY, P_HYX, 1.f, i - 1));
-    L.fn(EX)[id] = L.fo(EX)[id] + gx;
-    L.fn(EY)[id] = L.fo(EY)[id] + gy;
-    L.fn(EZ)[id] = L.fo(EZ)[id] + gz;
-    // λ_ψ of the H memories at this cell
+    const float ox = L.fo(EX)[id], oy = L.fo(EY)[id], oz = L.fo(EZ)[id];
+    // λ_ψ of the H memories at this cell. Every load comes before the first
+    // store: the compiler cannot tell the buffers apart, and a load after a
+    // store would wait for it.
     const int xs = slab_index(i, p.nx, p.npml), ys = slab_index(j, p.ny, p.npml);
+    float yx = 0.f, zx = 0.f, xy = 0.f, zy = 0.f;
+    size_t qx = 0, qy = 0;
     if (xs >= 0) {
         const float b = cx_tab(p, T_HB)[i];
-        const size_t q = psix_at(p, k, j, xs);
-        L.psi_new(P_HYX)[q] = b * (p.sx * L.v(HY, i, j, k) + L.psi_old(P_HYX)[q]);
-        L.psi_new(P_HZX)[q] = b * (-p.sx * L.v(HZ, i, j, k) + L.psi_old(P_HZX)[q]);
+        qx = psix_at(p, k, j, xs);
+        yx = b * (p.sx * L.v(HY, i, j, k) + L.psi_old(P_HYX)[qx]);
+        zx = b * (-p.sx * L.v(HZ, i, j, k) + L.psi_old(P_HZX)[qx]);
     }
     if (ys >= 0) {
         const float b = cy_tab(p, T_HB)[j];
-        const size_t q = psiy_at(p, k, ys, i);
-        L.psi_new(P_HXY)[q] = b * (-p.sy * L.v(HX, i, j, k) + L.psi_old(P_HXY)[q]);
-        L.psi_new(P_HZY)[q] = b * (p.sy * L.v(HZ, i, j, k) + L.psi_old(P_HZY)[q]);
+        qy = psiy_at(p, k, ys, i);
+        xy = b * (-p.sy * L.v(HX, i, j, k) + L.psi_old(P_HXY)[qy]);
+        zy = b * (p.sy * L.v(HZ, i, j, k) + L.psi_old(P_HZY)[qy]);
+    }
+    L.fn(EX)[id] = ox + gx;
+    L.fn(EY)[id] = oy + gy;
+    L.fn(EZ)[id] = oz + gz;
+    if (xs >= 0) {
+        L.psi_new(P_HYX)[qx] = yx;
+        L.psi_new(P_HZX)[qx] = zx;
+    }
+    if (ys >= 0) {
+        L.psi_new(P_HXY)[qy] = xy;
+        L.psi_new(P_HZY)[qy] = zy;
     }
 }
 
@@ -181,23 +194,35 @@ __global__ void __launch_bounds__(BT) adj_e_kernel(Problem p, int par, Frame fr,
                      (de_x(L, EZ, P_EZX, 1.f, i + 1) - de_x(L, EZ, P_EZX, 1.f, i));
     const float gz = -(de_y(L, EX, P_EXY, 1.f, j + 1) - de_y(L, EX, P_EXY, 1.f, j)) -
                      (de_x(L, EY, P_EYX, -1.f, i + 1) - de_x(L, EY, P_EYX, -1.f, i));
-    L.fn(HX)[id] = L.fo(HX)[id] + gx;
-    L.fn(HY)[id] = L.fo(HY)[id] + gy;
-    L.fn(HZ)[id] = L.fo(HZ)[id] + gz;
+    const float ox = L.fo(HX)[id], oy = L.fo(HY)[id], oz = L.fo(HZ)[id];
+    // every load before the first store, as in adj_h_kernel
     const int xs = slab_index(i, p.nx, p.npml), ys = slab_index(j, p.ny, p.npml);
+    float yx = 0.f, zx = 0.f, xy = 0.f, zy = 0.f;
+    size_t qx = 0, qy = 0;
     if (xs >= 0) {
         const float b = cx_tab(p, T_EB)[i];
-        const size_t q = psix_at(p, k, j, xs);
-        const float oy = L.psi_old(P_EYX)[q], oz = L.psi_old(P_EZX)[q];
-        L.psi_new(P_EYX)[q] = upd_e(p, EY, i, j) ? b * (-p.sx * L.v(EY, i, j, k) + oy) : oy;
-        L.psi_new(P_EZX)[q] = upd_e(p, EZ, i, j) ? b * (p.sx * L.v(EZ, i, j, k) + oz) : oz;
+        qx = psix_at(p, k, j, xs);
+        const float py = L.psi_old(P_EYX)[qx], pz = L.psi_old(P_EZX)[qx];
+        yx = upd_e(p, EY, i, j) ? b * (-p.sx * L.v(EY, i, j, k) + py) : py;
+        zx = upd_e(p, EZ, i, j) ? b * (p.sx * L.v(EZ, i, j, k) + pz) : pz;
     }
     if (ys >= 0) {
         const float b = cy_tab(p, T_EB)[j];
-        const size_t q = psiy_at(p, k, ys, i);
-        const float ox = L.psi_old(P_EXY)[q], oz = L.psi_old(P_EZY)[q];
-        L.psi_new(P_EXY)[q] = upd_e(p, EX, i, j) ? b * (p.sy * L.v(EX, i, j, k) + ox) : ox;
-        L.psi_new(P_EZY)[q] = upd_e(p, EZ, i, j) ? b * (-p.sy * L.v(EZ, i, j, k) + oz) : oz;
+        qy = psiy_at(p, k, ys, i);
+        const float px = L.psi_old(P_EXY)[qy], pz = L.psi_old(P_EZY)[qy];
+        xy = upd_e(p, EX, i, j) ? b * (p.sy * L.v(EX, i, j, k) + px) : px;
+        zy = upd_e(p, EZ, i, j) ? b * (-p.sy * L.v(EZ, i, j, k) + pz) : pz;
+    }
+    L.fn(HX)[id] = ox + gx;
+    L.fn(HY)[id] = oy + gy;
+    L.fn(HZ)[id] = oz + gz;
+    if (xs >= 0) {
+        L.psi_new(P_EYX)[qx] = yx;
+        L.psi_new(P_EZX)[qx] = zx;
+    }
+    if (ys >= 0) {
+        L.psi_new(P_EXY)[qy] = xy;
+        L.psi_new(P_EZY)[qy] = zy;
     }
 }
 
