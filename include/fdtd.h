@@ -172,7 +172,40 @@ int fdtd_fit_periodic_z(double wavelength, double theta, double dx, int32_t nz_h
  * fdtd_destroy. On failure *out is NULL. */
 int fdtd_create(const fdtd_grid *grid, fdtd_ctx **out);
 
-/* Free the context and all its device memory. NULL-safe. */
+/* Field layout of a grid on the device (pure host function; no GPU call).
+ * A field component is nz x ny rows of *pitch floats, x fastest; *pitch is
+ * nx rounded up to a multiple of 64 (256-byte rows) and the cells x >= nx of
+ * a row are padding that no kernel reads or writes. One parity holds the six
+ * components Ex, Ey, Ez, Hx, Hy, Hz in that order, one after another:
+ * *parity_floats = 6 nz ny pitch. Returns FDTD_EINVAL for a grid that
+ * fdtd_create would reject or NULL outputs. */
+int fdtd_field_layout(const fdtd_grid *grid, int32_t *pitch, int64_t *parity_floats);
+
+/* fdtd_create with the two ping-pong parities of the six field components in
+ * caller-owned device memory (for example two torch tensors), for callers
+ * that want the fields without copies. dev_fields[0] and dev_fields[1] each
+ * hold fdtd_field_layout's parity_floats floats; they must be device memory
+ * of the current device, 256-byte aligned and disjoint, and each must lie
+ * inside one device allocation (checked: FDTD_EINVAL otherwise; a buffer
+ * that is too short but sits inside a larger allocation, as a slice of a
+ * caching allocator's block can, is not detected and is overrun). The
+ * library zeroes them on the grid's stream during this call, reads and
+ * writes them on that stream while stepping and never frees them: they must
+ * outlive the context. The CPML memories, tables and every other buffer stay
+ * library-owned and count in fdtd_info.device_bytes; the two field buffers
+ * do not. Everything else behaves as for fdtd_create. */
+int fdtd_create_ext(const fdtd_grid *grid, float *const dev_fields[2], fdtd_ctx **out);
+
+/* Device address of the parity buffer that holds the current state
+ * (E^n and H̃^{n+1/2} after n steps; six components in the fdtd_field_layout
+ * layout): one of the two buffers of fdtd_create_ext, or a library-owned one.
+ * It changes with every step call (a two-step pass flips the parity once per
+ * pair), so query it after stepping; the contents are complete once the
+ * grid's stream has finished the steps. */
+int fdtd_current_fields(const fdtd_ctx *ctx, float **dev_ptr);
+
+/* Free the context and all its device memory (not the caller's buffers of
+ * fdtd_create_ext). NULL-safe. */
 int fdtd_destroy(fdtd_ctx *ctx);
 
 /* Message of the last failure on ctx (or of the last failed fdtd_create when

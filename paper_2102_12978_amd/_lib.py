@@ -86,6 +86,11 @@ _SIGS = {
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            c_double_p]),
     "fdtd_create": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(_CTX)]),
+    "fdtd_create_ext": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(_CTX)]),
+    "fdtd_field_layout": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "fdtd_current_fields": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_void_p)]),
     "fdtd_destroy": (ctypes.c_int, [_CTX]),
     "fdtd_last_error": (ctypes.c_char_p, [_CTX]),
     "fdtd_set_injector": (ctypes.c_int, [_CTX, ctypes.POINTER(Injector)]),

@@ -83,7 +83,11 @@ const char* fdtd_last_error(const fdtd_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_create_error.c_str();
 }
 
-int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
+namespace {
+
+// fdtd_create / fdtd_create_ext: ext is NULL (the library allocates the two
+// field parities) or the caller's two parity buffers.
+int create_impl(const fdtd_grid* grid, float* const* ext, fdtd_ctx** out) {
     if (!out) return FDTD_EINVAL;
     *out = nullptr;
     if (!grid) {
@@ -128,8 +132,38 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
             p.psx = (long long)psix_elems(p);
             p.psy = (long long)psiy_elems(p);
         }
+        if (ext) {
+            // Reject what the kernels could not use before anything runs on
+            // it: a buffer outside device memory of this device, misaligned,
+            // running past its allocation, or overlapping the other one.
+            const size_t bytes = 6 * field_elems(p) * sizeof(float);
+            for (int par = 0; par < 2; ++par) {
+                float* f = ext[par];
+                need(f != nullptr, "dev_fields[] must not be NULL");
+                need(((uintptr_t)f & 255u) == 0, "dev_fields[] must be 256-byte aligned");
+                hipPointerAttribute_t at{};
+                const bool dev = hipPointerGetAttributes(&at, f) == hipSuccess &&
+                                 at.type == hipMemoryTypeDevice && at.device == c->device;
+                hipDeviceptr_t base = nullptr;
+                size_t size = 0;
+                const bool inside =
+                    dev && hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)f) == hipSuccess &&
+                    (const char*)f + bytes <= (const char*)base + size;
+                (void)hipGetLastError();   // a failed query leaves no error behind
+                need(dev, "dev_fields[] must be device memory of the current device");
+                need(inside, "dev_fields[] buffer ends before the field layout does");
+            }
+            const char *a0 = (const char*)ext[0], *a1 = (const char*)ext[1];
+            need(a0 + bytes <= a1 || a1 + bytes <= a0, "dev_fields[0] and [1] overlap");
+        }
         for (int par = 0; par < 2; ++par) {
-            p.fbase[par] = dalloc<float>(c, 6 * field_elems(p));
+            if (ext) {
+                p.fbase[par] = ext[par];
+                check(hipMemsetAsync(ext[par], 0, 6 * field_elems(p) * sizeof(float), c->stream),
+                      "clear fields");
+            } else {
+                p.fbase[par] = dalloc<float>(c, 6 * field_elems(p));
+            }
             p.pbase[par] = p.npml > 0 ? dalloc<float>(c, psi_total(p)) : nullptr;
         }
         std::vector<float> tx[6], ty[6];
@@ -157,6 +191,34 @@ int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) {
         return rc;
     }
     *out = c;
+    return FDTD_OK;
+}
+
+}  // namespace
+
+int fdtd_create(const fdtd_grid* grid, fdtd_ctx** out) { return create_impl(grid, nullptr, out); }
+
+int fdtd_create_ext(const fdtd_grid* grid, float* const dev_fields[2], fdtd_ctx** out) {
+    if (!dev_fields) {
+        if (out) *out = nullptr;
+        g_create_error = "dev_fields is NULL";
+        return FDTD_EINVAL;
+    }
+    return create_impl(grid, dev_fields, out);
+}
+
+int fdtd_field_layout(const fdtd_grid* grid, int32_t* pitch, int64_t* parity_floats) {
+    if (!grid || !pitch || !parity_floats) return FDTD_EINVAL;
+    if (!validate_grid(*grid).empty()) return FDTD_EINVAL;
+    const int64_t pt = ((int64_t)grid->nx + 63) / 64 * 64;
+    *pitch = (int32_t)pt;
+    *parity_floats = 6 * (int64_t)grid->nz * grid->ny * pt;
+    return FDTD_OK;
+}
+
+int fdtd_current_fields(const fdtd_ctx* c, float** dev_ptr) {
+    if (!c || !dev_ptr) return FDTD_EINVAL;
+    *dev_ptr = c->p.fbase[c->parity];
     return FDTD_OK;
 }
 

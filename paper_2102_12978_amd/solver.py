@@ -34,17 +34,46 @@ def _fptr(a):
     return a.ctypes.data_as(L.c_float_p)
 
 
+def _grid(nx, ny, nz, dx, dy, dz, courant, bc, cpml_cells, grade, sigma_scale, kappa_max,
+          alpha_max, kernel, stream):
+    return L.Grid(nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz, courant=courant, bc_xy=bc,
+                  cpml_cells=cpml_cells, cpml_grade=grade, cpml_sigma_scale=sigma_scale,
+                  cpml_kappa_max=kappa_max, cpml_alpha_max=alpha_max, kernel=kernel,
+                  reserved=0, stream=stream)
+
+
+def field_layout(nx, ny, nz, dx, dy, dz, courant=0.5, bc=L.BC_CPML, cpml_cells=0, grade=3.0,
+                 sigma_scale=1.0, kappa_max=1.0, alpha_max=0.0):
+    """(pitch, floats per parity) of the device field layout (fdtd_field_layout)."""
+    lib = L.load()
+    g = _grid(nx, ny, nz, dx, dy, dz, courant, bc, cpml_cells, grade, sigma_scale, kappa_max,
+              alpha_max, L.KERNEL_AUTO, None)
+    pitch = ctypes.c_int32()
+    n = ctypes.c_int64()
+    rc = lib.fdtd_field_layout(ctypes.byref(g), ctypes.byref(pitch), ctypes.byref(n))
+    if rc != L.OK:
+        raise L.FdtdError(rc, "fdtd_field_layout rejected the grid")
+    return pitch.value, n.value
+
+
 class Solver:
+    """dev_fields: None (the library allocates the fields) or the device
+    addresses of two caller-owned parity buffers laid out as field_layout()
+    says (fdtd_create_ext); the caller keeps them alive while the solver
+    exists."""
+
     def __init__(self, nx, ny, nz, dx, dy, dz, courant=0.5, bc=L.BC_CPML, cpml_cells=0,
                  grade=3.0, sigma_scale=1.0, kappa_max=1.0, alpha_max=0.0,
-                 kernel=L.KERNEL_AUTO, stream=None):
+                 kernel=L.KERNEL_AUTO, stream=None, dev_fields=None):
         self._lib = L.load()
-        g = L.Grid(nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz, courant=courant, bc_xy=bc,
-                   cpml_cells=cpml_cells, cpml_grade=grade, cpml_sigma_scale=sigma_scale,
-                   cpml_kappa_max=kappa_max, cpml_alpha_max=alpha_max, kernel=kernel,
-                   reserved=0, stream=stream)
+        g = _grid(nx, ny, nz, dx, dy, dz, courant, bc, cpml_cells, grade, sigma_scale,
+                  kappa_max, alpha_max, kernel, stream)
         ctx = ctypes.c_void_p()
-        rc = self._lib.fdtd_create(ctypes.byref(g), ctypes.byref(ctx))
+        if dev_fields is None:
+            rc = self._lib.fdtd_create(ctypes.byref(g), ctypes.byref(ctx))
+        else:
+            ptrs = (ctypes.c_void_p * 2)(int(dev_fields[0]), int(dev_fields[1]))
+            rc = self._lib.fdtd_create_ext(ctypes.byref(g), ptrs, ctypes.byref(ctx))
         if rc != L.OK:
             raise L.FdtdError(rc, self._lib.fdtd_last_error(None).decode())
         self._ctx = ctx
@@ -66,15 +95,28 @@ class Solver:
         return s
 
     # -- construction from a shared workload description ------------------
-    @classmethod
-    def from_workload(cls, w: W.Workload, bc=None, kernel=L.KERNEL_AUTO, stream=None):
+    @staticmethod
+    def workload_grid_args(w: W.Workload, bc=None):
+        """Positional and keyword arguments of Solver / field_layout for a
+        workload (z fitted to whole axial periods)."""
         nz, dz = fit_periodic_z(W.WAVELENGTH, w.theta, w.dx, w.nz_hint)
         bc = w.bc if bc is None else bc
-        s = cls(w.nx, w.ny, nz, w.dx, w.dx, dz, courant=w.courant, bc=bc,
-                cpml_cells=w.npml if bc == L.BC_CPML else 0, grade=w.grade,
-                sigma_scale=w.sigma_scale, kappa_max=w.kappa_max, alpha_max=w.alpha_max,
-                kernel=kernel, stream=stream)
-        return s
+        return ((w.nx, w.ny, nz, w.dx, w.dx, dz),
+                dict(courant=w.courant, bc=bc, cpml_cells=w.npml if bc == L.BC_CPML else 0,
+                     grade=w.grade, sigma_scale=w.sigma_scale, kappa_max=w.kappa_max,
+                     alpha_max=w.alpha_max))
+
+    @classmethod
+    def from_workload(cls, w: W.Workload, bc=None, kernel=L.KERNEL_AUTO, stream=None,
+                      dev_fields=None):
+        args, kw = cls.workload_grid_args(w, bc)
+        return cls(*args, kernel=kernel, stream=stream, dev_fields=dev_fields, **kw)
+
+    def current_fields(self):
+        """Device address of the parity buffer holding the current state."""
+        ptr = ctypes.c_void_p()
+        self._c(self._lib.fdtd_current_fields(self._ctx, ctypes.byref(ptr)))
+        return ptr.value or 0
 
     def set_workload_injector(self, w: W.Workload, sector_amp=None, sector_phase=None):
         kind, a, b = w.ramp_args

@@ -9,7 +9,7 @@ import pytest
 
 from oracle import problem as P
 from paper_2102_12978_amd import _lib as L
-from paper_2102_12978_amd.solver import Solver, fit_periodic_z
+from paper_2102_12978_amd.solver import Solver, field_layout, fit_periodic_z
 
 
 def test_library_exports_every_declared_symbol():
@@ -70,6 +70,39 @@ def test_null_arguments_are_rejected():
     assert lib.fdtd_destroy(None) == L.OK
     assert lib.fdtd_step(None, 1) == L.EINVAL
     assert lib.fdtd_get_info(None, None) == L.EINVAL
+
+
+@pytest.mark.parametrize("nx,ny,nz,pitch", [(32, 32, 32, 64), (65, 40, 7, 128),
+                                             (768, 768, 255, 768), (130, 64, 1, 192)])
+def test_field_layout(nx, ny, nz, pitch):
+    """Rows padded to 256 bytes; one parity is the six components back to
+    back (pure host function)."""
+    p, n = field_layout(nx, ny, nz, 5e-8, 5e-8, 5.07e-8, cpml_cells=8)
+    assert p == pitch
+    assert n == 6 * nz * ny * pitch
+
+
+def test_external_field_entry_points_validate_on_the_host():
+    lib = L.load()
+    ctx = ctypes.c_void_p()
+    g = L.Grid(nx=32, ny=32, nz=32, dx=5e-8, dy=5e-8, dz=5.07e-8, courant=0.7, bc_xy=L.BC_CPML,
+               cpml_cells=8, cpml_grade=3.0, cpml_sigma_scale=1.0, cpml_kappa_max=1.0,
+               cpml_alpha_max=0.0, kernel=L.KERNEL_AUTO, reserved=0, stream=None)
+    pitch, n = ctypes.c_int32(), ctypes.c_int64()
+    assert lib.fdtd_field_layout(ctypes.byref(g), ctypes.byref(pitch), ctypes.byref(n)) == L.EINVAL
+    g.courant = 0.5
+    assert lib.fdtd_field_layout(ctypes.byref(g), None, ctypes.byref(n)) == L.EINVAL
+    assert lib.fdtd_field_layout(None, ctypes.byref(pitch), ctypes.byref(n)) == L.EINVAL
+    assert lib.fdtd_create_ext(ctypes.byref(g), None, ctypes.byref(ctx)) == L.EINVAL
+    assert b"dev_fields" in lib.fdtd_last_error(None)
+    assert ctx.value is None
+    ptr = ctypes.c_void_p()
+    assert lib.fdtd_current_fields(None, ctypes.byref(ptr)) == L.EINVAL
+    # the grid is validated before any pointer or the GPU is looked at
+    with pytest.raises(L.FdtdError) as e:
+        Solver(32, 32, 32, 5e-8, 5e-8, 5.07e-8, courant=0.7, cpml_cells=8,
+               dev_fields=(256, 512))
+    assert e.value.code == L.EINVAL and "Courant" in str(e.value)
 
 
 def test_stream_probe_validates_before_touching_the_gpu():
