@@ -67,6 +67,14 @@ extern "C" {
 #define FDTD_POL_Y_TM 4
 #define FDTD_POL_Z_TM 5
 
+/* ---- injector flags (fdtd_injector.flags) ---------------------------------
+ * FDTD_INJ_ALLOW_Z_MISFIT: accept a z length that holds a fractional number
+ * of axial periods λ_z = λ / cos θ (for example nz from the truncation
+ * int(p λ_z / Δz) of §4's sampling rule instead of fdtd_fit_periodic_z). z
+ * stays periodic, so the injected phase e^{iβz} then jumps where the box
+ * wraps; without the flag such a box is rejected. */
+#define FDTD_INJ_ALLOW_Z_MISFIT 1
+
 /* ---- kernel choice ------------------------------------------------------ */
 #define FDTD_KERNEL_AUTO  0   /* fused kernel, tile shape from the autotuner  */
 #define FDTD_KERNEL_SPLIT 1   /* two kernels per step (E, then H)            */
@@ -132,6 +140,7 @@ typedef struct fdtd_injector {
     int32_t polarization;     /* FDTD_POL_* (0: Π_x TE, the paper's runs)      */
     const double *sector_amp;   /* host [n_sectors] amplitudes a_s, or NULL    */
     const double *sector_phase; /* host [n_sectors] phases φ_s (rad), or NULL  */
+    int32_t flags;            /* FDTD_INJ_* bits; 0 = none                       */
 } fdtd_injector;
 
 typedef struct fdtd_info {
@@ -221,7 +230,8 @@ const char *fdtd_last_error(const fdtd_ctx *ctx);
  * n_sectors > 0 the weight w_s = a_s e^{iφ_s} of the sector
  * s = floor(n_sectors φ_c / 2π) of the point's azimuth multiplies Ã_c.
  * Requires an integer number of axial periods in the box (|β nz Δz / 2π -
- * round| <= 1e-6). inj == NULL removes the antenna. */
+ * round| <= 1e-6) unless inj->flags holds FDTD_INJ_ALLOW_Z_MISFIT; unknown
+ * flag bits are rejected. inj == NULL removes the antenna. */
 int fdtd_set_injector(fdtd_ctx *ctx, const fdtd_injector *inj);
 
 /* Replace the sector weights of the installed antenna (host arrays of n

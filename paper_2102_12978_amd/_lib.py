@@ -12,6 +12,7 @@ RAMP_SIN2, RAMP_GAUSS, RAMP_CW = 0, 1, 2
 KERNEL_AUTO, KERNEL_SPLIT, KERNEL_FUSED = 0, 1, 2
 FRAME_SPLIT, FRAME_FUSED = 0, 1
 POL_X_TE, POL_Y_TE, POL_Z_TE, POL_X_TM, POL_Y_TM, POL_Z_TM = range(6)
+INJ_ALLOW_Z_MISFIT = 1
 EX, EY, EZ, HX, HY, HZ = range(6)
 PSI_EXY, PSI_EYX, PSI_EZX, PSI_EZY, PSI_HXY, PSI_HYX, PSI_HZX, PSI_HZY = range(6, 14)
 DIAG_EX2, DIAG_EY2, DIAG_EZ2, DIAG_ENERGY = 1, 2, 4, 8
@@ -38,7 +39,7 @@ class Injector(ctypes.Structure):
                 ("axis_y", ctypes.c_double), ("ramp_a", ctypes.c_double),
                 ("ramp_b", ctypes.c_double), ("n_sectors", ctypes.c_int32),
                 ("polarization", ctypes.c_int32), ("sector_amp", c_double_p),
-                ("sector_phase", c_double_p)]
+                ("sector_phase", c_double_p), ("flags", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

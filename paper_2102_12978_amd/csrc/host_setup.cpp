@@ -164,9 +164,12 @@ std::string build_antenna(const fdtd_grid& g, int /*pitch*/, double ry, double r
     a.e0 = inj.e0;
     a.order = inj.order;
     a.theta = inj.theta;
-    // the z phase must be periodic over the box
+    if (inj.flags & ~FDTD_INJ_ALLOW_Z_MISFIT) return "unknown injector flags";
+    // the z phase must be periodic over the box, unless the caller accepts
+    // the jump at the wrap
     double periods = a.beta * g.nz * rz / (2.0 * kPi);
-    if (std::fabs(periods - round_half_up(periods)) > 1e-6 || round_half_up(periods) < 1) {
+    if (!(inj.flags & FDTD_INJ_ALLOW_Z_MISFIT) &&
+        (std::fabs(periods - round_half_up(periods)) > 1e-6 || round_half_up(periods) < 1)) {
         char buf[200];
         std::snprintf(buf, sizeof buf,
                       "box length holds %.9f axial periods; use fdtd_fit_periodic_z", periods);

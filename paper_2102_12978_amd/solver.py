@@ -118,12 +118,13 @@ class Solver:
         self._c(self._lib.fdtd_current_fields(self._ctx, ctypes.byref(ptr)))
         return ptr.value or 0
 
-    def set_workload_injector(self, w: W.Workload, sector_amp=None, sector_phase=None):
+    def set_workload_injector(self, w: W.Workload, sector_amp=None, sector_phase=None,
+                              allow_z_misfit=False):
         kind, a, b = w.ramp_args
         self.set_injector(W.WAVELENGTH, w.theta, w.order, w.e0, w.r_outer_cells * w.dx,
                           w.thickness_cells * w.dx, ramp_kind=kind, ramp_a=a, ramp_b=b,
                           sector_amp=sector_amp, sector_phase=sector_phase,
-                          polarization=w.polarization)
+                          polarization=w.polarization, allow_z_misfit=allow_z_misfit)
 
     # -- API --------------------------------------------------------------
     def close(self):
@@ -149,11 +150,12 @@ class Solver:
     def set_injector(self, wavelength, theta, order, e0, r_outer, thickness,
                      ramp_kind=L.RAMP_SIN2, ramp_a=0.0, ramp_b=0.0, axis_x=math.nan,
                      axis_y=math.nan, sector_amp=None, sector_phase=None,
-                     polarization=L.POL_X_TE):
+                     polarization=L.POL_X_TE, allow_z_misfit=False):
         inj = L.Injector(wavelength=wavelength, theta=theta, order=order, ramp_kind=ramp_kind,
                          e0=e0, r_outer=r_outer, thickness=thickness, axis_x=axis_x,
                          axis_y=axis_y, ramp_a=ramp_a, ramp_b=ramp_b, n_sectors=0,
-                         polarization=polarization)
+                         polarization=polarization,
+                         flags=L.INJ_ALLOW_Z_MISFIT if allow_z_misfit else 0)
         keep = []
         if sector_amp is not None:
             a = np.ascontiguousarray(sector_amp, dtype=np.float64)

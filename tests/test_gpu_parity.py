@@ -265,6 +265,30 @@ def test_autotune_leaves_state_alone():
     r.close()
 
 
+def test_z_misfit_needs_the_flag_and_matches_the_oracle():
+    """A box three planes longer than the whole-period fit (a fractional
+    number of axial periods): the antenna is refused without
+    FDTD_INJ_ALLOW_Z_MISFIT, and with it the run (the injected phase jumps at
+    the z wrap) matches the oracle on the same box."""
+    from paper_2102_12978_amd.solver import Solver
+    w = W.parity_small()
+    nz_fit, dz = P.fit_periodic_z(W.WAVELENGTH, w.theta, w.dx, w.nz_hint)
+    nz = nz_fit + 3
+    args, kw = Solver.workload_grid_args(w)
+    s = Solver(w.nx, w.ny, nz, w.dx, w.dx, dz, kernel=L.KERNEL_FUSED, **kw)
+    with pytest.raises(L.FdtdError) as e:
+        s.set_workload_injector(w)
+    assert e.value.code == L.EINVAL and "axial periods" in str(e.value)
+    s.set_workload_injector(w, allow_z_misfit=True)
+    print(f"[gpu case] {w.name}: nz {nz} instead of {nz_fit}", flush=True)
+    s.step(w.steps)
+    g = cases.oracle_grid(w, nz=nz, dz=dz)
+    ant = P.build_antenna(g, cases.oracle_injector(w))
+    st = Y.run(g, w.steps, ant)
+    _compare(s, st, g)
+    s.close()
+
+
 def test_source_linearity_on_gpu():
     w = W.parity_small()
     w.steps = 30

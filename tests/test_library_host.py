@@ -128,7 +128,8 @@ def test_polarisation_constants_match_the_header():
     for name, value in (("FDTD_POL_X_TE", L.POL_X_TE), ("FDTD_POL_Y_TE", L.POL_Y_TE),
                         ("FDTD_POL_Z_TE", L.POL_Z_TE), ("FDTD_POL_X_TM", L.POL_X_TM),
                         ("FDTD_POL_Y_TM", L.POL_Y_TM), ("FDTD_POL_Z_TM", L.POL_Z_TM),
-                        ("FDTD_FRAME_SPLIT", L.FRAME_SPLIT), ("FDTD_FRAME_FUSED", L.FRAME_FUSED)):
+                        ("FDTD_FRAME_SPLIT", L.FRAME_SPLIT), ("FDTD_FRAME_FUSED", L.FRAME_FUSED),
+                        ("FDTD_INJ_ALLOW_Z_MISFIT", L.INJ_ALLOW_Z_MISFIT)):
         assert f"#define {name} {value}" in text, name
 
 
