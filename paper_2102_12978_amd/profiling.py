@@ -29,8 +29,13 @@ def kernel_sha256_16(path=KERNEL_SRC):
 
 
 def source_of(kernel):
-    """Source file of an interior kernel (by the name the counters carry)."""
-    return os.path.join(CSRC, "kernels_fused2.hip" if "fused2" in kernel else "kernels_fused.hip")
+    """Source file of a kernel (by the name the counters carry): the two-step
+    and one-step interior kernels, or the split frame kernels."""
+    if "fused2" in kernel:
+        return os.path.join(CSRC, "kernels_fused2.hip")
+    if "split_" in kernel:
+        return os.path.join(CSRC, "kernels_split.hip")
+    return os.path.join(CSRC, "kernels_fused.hip")
 
 
 def short_name(name):
