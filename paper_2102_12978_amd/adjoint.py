@@ -93,13 +93,15 @@ class SectorSensitivity:
     carries per-sector weights (workload.extra['sectors'])."""
 
     def __init__(self, w: W.Workload, checkpoint_every=None, n_sectors=None, stream=None,
-                 plane=None, window_begin=None, steps=None, kernel=L.KERNEL_FUSED):
+                 plane=None, window_begin=None, steps=None, kernel=L.KERNEL_FUSED,
+                 dev_fields=None):
         self.w = w
         self.n_sectors = n_sectors or w.extra.get("sectors", 256)
         self.every = checkpoint_every or w.extra.get("checkpoint_every", 100)
         self.steps = steps or w.steps
         self.window_begin = self.steps - w.window_steps if window_begin is None else window_begin
-        self.solver = Solver.from_workload(w, kernel=kernel, stream=stream)
+        self.solver = Solver.from_workload(w, kernel=kernel, stream=stream,
+                                           dev_fields=dev_fields)
         ones = np.ones(self.n_sectors)
         self.solver.set_workload_injector(w, sector_amp=ones, sector_phase=0 * ones)
         self.plane = self.solver.nz // 2 if plane is None else plane
