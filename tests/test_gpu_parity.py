@@ -289,6 +289,47 @@ def test_z_misfit_needs_the_flag_and_matches_the_oracle():
     s.close()
 
 
+@pytest.mark.parametrize("nx,ny,nz,bc,npml", [(2, 2, 1, P.BC_PERIODIC, 0), (2, 2, 1, P.BC_PEC, 0),
+                                             (3, 5, 2, P.BC_PEC, 0), (4, 4, 1, P.BC_CPML, 1),
+                                             (5, 3, 2, P.BC_CPML, 1)])
+def test_degenerate_grids(nx, ny, nz, bc, npml):
+    """The smallest grids the library accepts (2×2×1; one-cell CPML on
+    4 and 3 cells; one plane, so the z neighbours are the plane itself):
+    no interior, the split kernels take every cell. A zero-step call changes
+    nothing, a negative one is refused, and seven steps from a seeded random
+    start match the oracle, CPML memories included."""
+    from paper_2102_12978_amd.solver import Solver
+    w = W.Workload(f"tiny_{nx}x{ny}x{nz}", nx, ny, nz, 16.0, 10.0, 0, 1.0, 0.5, npml, 7, bc=bc)
+    g = cases.oracle_grid(w, bc=bc, nz=nz, dz=w.dx)
+    st = Y.zero_state(g)
+    for c, a in zip(GC.COMPS, W.random_fields((nz, ny, nx), 4)):
+        st.f[c] = a.astype(np.float32).astype(np.float64)
+    if bc != P.BC_PERIODIC:
+        for c in ("ex", "ey", "ez"):
+            st.f[c][:, Y.held_mask(g, c)] = 0.0
+    print(f"[gpu case] {w.name} bc={bc} npml={npml}", flush=True)
+    s = Solver(nx, ny, nz, w.dx, w.dx, w.dx, courant=w.courant, bc=bc, cpml_cells=npml,
+               grade=w.grade, sigma_scale=w.sigma_scale, kappa_max=w.kappa_max,
+               alpha_max=w.alpha_max, kernel=L.KERNEL_FUSED)
+    assert s.info().interior_cells == 0
+    for i, c in enumerate(GC.COMPS):
+        s.set_state(i, st.f[c].astype(np.float32))
+    before = [s.get_state(i) for i in range(6)]
+    s.step(0)
+    assert s.info().step == 0
+    assert all(np.array_equal(b, s.get_state(i)) for i, b in enumerate(before))
+    with pytest.raises(L.FdtdError) as e:
+        s.step(-1)
+    assert e.value.code == L.EINVAL
+    cp = P.cpml_tables(g)
+    for _ in range(7):
+        Y.step(st, g, cp, None)
+    s.step(7)
+    assert s.info().step == 7
+    _compare(s, st, g, psi=npml > 0)
+    s.close()
+
+
 def test_source_linearity_on_gpu():
     w = W.parity_small()
     w.steps = 30
