@@ -161,3 +161,22 @@ def test_batch64_sampled_instances():
         ref, _ = _single(ws[q], 24)
         assert _same(b[q].fields(), ref), ws[q].name
     b.close()
+
+
+def test_single_instance_batch_and_step_counts():
+    """A batch of one instance equals its single split run; zero steps
+    change nothing and a negative count is refused."""
+    w = W.batch_small()[0]
+    b = Batch([w])
+    b.set_graph_steps(20)
+    before = b[0].fields()
+    b.step(0)
+    assert b.info().step == 0
+    assert _same(before, b[0].fields())
+    with pytest.raises(L.FdtdError) as e:
+        b.step(-1)
+    assert e.value.code == L.EINVAL
+    b.step(23)            # one graph replay and three direct steps
+    ref, _ = _single(w, 23)
+    assert _same(b[0].fields(), ref)
+    b.close()

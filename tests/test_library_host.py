@@ -105,6 +105,16 @@ def test_external_field_entry_points_validate_on_the_host():
     assert e.value.code == L.EINVAL and "Courant" in str(e.value)
 
 
+def test_batch_create_rejects_empty_batches_on_the_host():
+    lib = L.load()
+    out = ctypes.c_void_p()
+    assert lib.fdtd_batch_create(0, None, None, None, ctypes.byref(out)) == L.EINVAL
+    assert out.value is None
+    assert b"count" in lib.fdtd_batch_last_error(None)
+    assert lib.fdtd_batch_create(-3, None, None, None, ctypes.byref(out)) == L.EINVAL
+    assert lib.fdtd_batch_step(None, 1) == L.EINVAL
+
+
 def test_stream_probe_validates_before_touching_the_gpu():
     lib = L.load()
     ms, gbs = ctypes.c_double(), ctypes.c_double()
