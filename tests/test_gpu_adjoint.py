@@ -296,3 +296,40 @@ def test_grad192_gradient_vs_finite_differences():
     assert abs(loss - fd["loss"]) <= 1e-4 * fd["loss"]
     assert err < 1e-3
     sens.close()
+
+
+def test_adjoint_refuses_calls_out_of_order_and_bad_arguments():
+    """ESTATE: backward before a forward, a forward context without an
+    antenna. EINVAL: empty runs, a window outside the run, a plane outside
+    the grid, a dL/dI of the wrong size, a wrong sector count, a negative
+    transpose count. The context stays usable after every refusal."""
+    w = W.Workload("adj_120_m0", 120, 120, 10, 12.0, 30.0, 0, 40.0, 2.0, 6, 90,
+                   ramp_periods=2.0, extra={"sectors": 16, "checkpoint_every": 25})
+    sens = SectorSensitivity(w, window_begin=60)
+    adj, s = sens.adj, sens.solver
+    nxy = s.nx * s.ny
+
+    def code(fn, *args):
+        with pytest.raises(L.FdtdError) as e:
+            fn(*args)
+        return e.value.code
+
+    assert code(adj.backward, np.zeros((s.ny, s.nx)), 16) == L.ESTATE
+    assert code(adj.forward, 0, sens.plane, 0) == L.EINVAL
+    assert code(adj.forward, 90, sens.plane, 90) == L.EINVAL
+    assert code(adj.forward, 90, s.nz, 60) == L.EINVAL
+    assert code(adj.forward, 90, -1, 60) == L.EINVAL
+    assert code(adj.transpose, -1) == L.EINVAL
+    ibar = sens.intensity(np.ones(16), np.zeros(16))
+    assert ibar.shape == (s.ny, s.nx)
+    assert code(adj.backward, np.zeros(nxy - 1), 16) == L.EINVAL
+    assert code(adj.backward, np.zeros(nxy), 8) == L.EINVAL
+    ga, gp = sens.backward(np.full((s.ny, s.nx), 1e-3))
+    assert np.all(np.isfinite(ga)) and np.all(np.isfinite(gp)) and np.any(ga != 0)
+    sens.close()
+    # an adjoint on a context without an antenna cannot run its forward
+    bare = GC.gpu_solver(w, inject=False)
+    a2 = Adjoint(bare, 25)
+    assert code(a2.forward, 90, bare.nz // 2, 60) == L.ESTATE
+    a2.close()
+    bare.close()
