@@ -417,3 +417,50 @@ def test_polarisations(pol, order):
     g, st = GC.oracle_run(w, w.steps)
     _compare(s, st, g)
     s.close()
+
+
+def test_forward_calls_refuse_bad_arguments():
+    """Every refusal is an error code with a message and changes nothing:
+    diagnostics outside the grid or with unknown bits, fluence and state
+    buffers of the wrong length or kind, sector weights without sectors or
+    of the wrong count, the energy before it was enabled."""
+    import ctypes
+    w = W.parity_small()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    lib, ctx = s._lib, s._ctx
+
+    def code(fn, *args):
+        with pytest.raises(L.FdtdError) as e:
+            fn(*args)
+        assert str(e.value)
+        return e.value.code
+
+    assert code(s.set_diagnostics, s.nz, 0, L.DIAG_EY2) == L.EINVAL
+    assert code(s.set_diagnostics, -2, 0, 0) == L.EINVAL
+    assert code(s.set_diagnostics, 0, -1, L.DIAG_EY2) == L.EINVAL
+    assert code(s.set_diagnostics, 0, 0, 1 << 4) == L.EINVAL
+    assert code(s.set_diagnostics, -1, 0, L.DIAG_EY2) == L.EINVAL
+    assert code(s.energy) == L.ESTATE
+    s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
+    s.step(3)
+    small = np.empty(s.nx * s.ny - 1, dtype=np.float32)
+    p = small.ctypes.data_as(L.c_float_p)
+    assert lib.fdtd_fluence(ctx, L.DIAG_EY2, p, small.size) == L.EINVAL
+    assert lib.fdtd_fluence(ctx, 3, p, s.nx * s.ny) == L.EINVAL
+    assert lib.fdtd_get_state(ctx, L.EY, p, small.size) == L.EINVAL
+    assert lib.fdtd_get_state(ctx, 99, p, small.size) == L.EINVAL
+    assert lib.fdtd_set_state(ctx, L.EY, p, small.size) == L.EINVAL
+    assert code(s.set_sector_weights, np.ones(4), np.zeros(4)) == L.EINVAL
+    # the run goes on as if nothing had been asked
+    ref = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    ref.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
+    ref.step(3)
+    s.step(4)
+    ref.step(4)
+    assert all(np.array_equal(a, b) for a, b in zip(s.fields(), ref.fields()))
+    assert np.array_equal(s.fluence(L.DIAG_EY2), ref.fluence(L.DIAG_EY2))
+    s.close()
+    ref.close()
+    bare = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, inject=False)
+    assert code(bare.set_sector_weights, np.ones(4), np.zeros(4)) == L.ESTATE
+    bare.close()
