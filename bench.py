@@ -49,33 +49,78 @@ def measured_traffic(name):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(w):
-    """The FP64 NumPy oracle on a bounded sample of the same workload: one
-    full step of the 768×768×255 grid (antenna and CPML included)."""
+def _oracle_leg(args):
+    """One CPU leg (worker process): `steps` FP64 oracle steps of workload
+    `name` (instances of the batch one after another). Returns (cells x steps,
+    seconds)."""
+    name, steps, per_instance = args
     from oracle import problem as P
     from oracle import yee as Y
-    nz, dz = P.fit_periodic_z(800e-9, w.theta, w.dx, w.nz_hint)
-    g = P.Grid(w.nx, w.ny, nz, w.dx, w.dx, dz, w.courant, P.BC_CPML, w.npml, w.grade,
-               w.sigma_scale, w.kappa_max, w.alpha_max)
-    inj = P.Injector(800e-9, w.theta, w.order, w.e0, w.r_outer_cells * w.dx,
-                     w.thickness_cells * w.dx, ramp_kind=P.RAMP_SIN2, ramp_a=w.ramp_seconds)
-    ant = P.build_antenna(g, inj)
-    cp = P.cpml_tables(g)
-    st = Y.zero_state(g)
-    steps = 3
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        Y.step(st, g, cp, ant)
-    dt = time.perf_counter() - t0
-    cells = g.nx * g.ny * g.nz
+    from paper_2102_12978_amd import workloads as W
+    ws = W.batch64_instances() if name == "batch64" else [getattr(W, name)()]
+    if per_instance is not None:
+        ws = ws[:per_instance]
+    upd, secs = 0, 0.0
+    for w in ws:
+        nz, dz = P.fit_periodic_z(W.WAVELENGTH, w.theta, w.dx, w.nz_hint)
+        g = P.Grid(w.nx, w.ny, nz, w.dx, w.dx, dz, w.courant, P.BC_CPML, w.npml, w.grade,
+                   w.sigma_scale, w.kappa_max, w.alpha_max)
+        kind, a, b = w.ramp_args
+        inj = P.Injector(W.WAVELENGTH, w.theta, w.order, w.e0, w.r_outer_cells * w.dx,
+                         w.thickness_cells * w.dx, ramp_kind=kind, ramp_a=a, ramp_b=b)
+        ant = P.build_antenna(g, inj)
+        cp = P.cpml_tables(g)
+        st = Y.zero_state(g)
+        n = min(steps, w.steps)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            Y.step(st, g, cp, ant)
+        secs += time.perf_counter() - t0
+        upd += g.nx * g.ny * g.nz * n
+    return upd, secs
+
+
+# (workload, steps, instances) of each CPU leg: the 768x768x255 benchmark
+# grid for the headline figure, and bounded samples of the other workloads.
+CPU_LEGS = {
+    "grid768": ("grid768", 3, None),
+    "cube32": ("cube32", 200, None),
+    "grad192": ("grad192", 100, None),
+    "batch64": ("batch64", 5, 8),
+}
+CPU_LEGS_FULL = {
+    "grid768": ("grid768", 20, None),
+    "cube32": ("cube32", 200, None),
+    "grad192": ("grad192", 1500, None),
+    "batch64": ("batch64", 50, None),
+}
+
+
+def cpu_baseline(full=False):
+    """The FP64 NumPy oracle timed on this host, one single-threaded process
+    per leg (legs in parallel): the 768x768x255 grid (value) and samples of
+    the 32^3, 192x192x61 and batch workloads (legs)."""
+    from concurrent.futures import ProcessPoolExecutor
+    legs = CPU_LEGS_FULL if full else CPU_LEGS
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
         avail = os.cpu_count()
-    return {"value": cells * steps / dt / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+    workers = max(1, min(len(legs), avail))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        res = dict(zip(legs, ex.map(_oracle_leg, legs.values())))
+    out = {}
+    for k, (name, steps, inst) in legs.items():
+        upd, secs = res[k]
+        out[k] = {"value": round(upd / secs / 1e9, 5), "unit": "Gcell-updates/s",
+                  "steps": steps, "instances": inst, "seconds": round(secs, 1)}
+    head = out["grid768"]
+    return {"value": head["value"], "unit": "Gcell-updates/s", "cores": 1,
             "cores_available": avail, "kind": "oracle",
-            "sample": f"{steps} full steps of the {g.nx}x{g.ny}x{g.nz} grid in FP64 NumPy "
-                      f"(single-threaded elementwise), {dt:.1f} s"}
+            "sample": f"{legs['grid768'][1]} full steps of the 768x768x255 grid in FP64 "
+                      f"NumPy, one single-threaded process ({head['seconds']} s); other legs "
+                      f"ran at the same time, one process each ({workers} processes)",
+            "legs": out}
 
 
 def batch_measure(torch, stream, steps=1000, warmup=20):
@@ -224,7 +269,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--reps", type=int, default=5,
+                    help="timed runs of --steps steps; the median one gives the value")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="CPU legs at their full lengths (minutes)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile shape")
     ap.add_argument("--rows", type=int, default=0, help="fix the tile rows (skips autotune)")
     ap.add_argument("--zchunk", type=int, default=0, help="z chunk with --rows")
@@ -268,42 +317,56 @@ def main():
     torch.cuda.synchronize()
     info = s.info()
 
-    s.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    s.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    prof = s.profile_read()
-    s.profile(False)
+    # the headline: args.reps timed runs of exactly args.steps steps each,
+    # no per-launch events; value from the median run
+    runs = []
+    for _ in range(args.reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        s.step(args.steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(ev0.elapsed_time(ev1))
+    total_ms = sorted(runs)[len(runs) // 2]
     ms_per_step = total_ms / args.steps
     value = cells * args.steps / (total_ms * 1e-3) / 1e9
-    log(f"[bench] {args.steps} steps in {total_ms:.1f} ms -> {value:.1f} Gcell/s; "
-        f"kernels: {prof}")
+    log(f"[bench] {args.reps} x {args.steps} steps: " +
+        ", ".join(f"{r:.1f}" for r in runs) + f" ms -> median {value:.1f} Gcell/s")
+
+    # per-kernel launch times: one more run of args.steps steps with a HIP
+    # event pair around every launch, on the solver's stream
+    s.profile(True)
+    torch.cuda.synchronize()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    prof = s.profile_read()
+    s.profile(False)
+    log(f"[bench] kernels: {prof}")
 
     # the dominant kernel: the interior kernel that ran (the two-step one
     # when pairs of steps go through it)
-    kname = next((k for k in ("fused2_interior", "fused_interior") if k in prof), None)
+    kname = next((k for k in KERNELS if k in prof), None)
     roof = None
     if kname:
         kin = prof[kname]
         avg_ms = kin[1] / kin[0]
-        # algorithmic bytes: one read and one write of the six components of
-        # every interior cell per launch (a two-step launch advances them twice)
-        bytes_launch = BYTES_PER_CELL * info.interior_cells
-        achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         upd = KERNELS[kname][2]
+        ncell = info.interior_cells
+        # algorithmic bytes: 48 B per cell-update (one read and one write of
+        # the six components), times the cell-updates of one launch
+        bytes_launch = BYTES_PER_CELL * upd * ncell
+        achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname), "kernel": kname,
-                "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": info.interior_cells,
-                "cell_updates_per_launch": upd * info.interior_cells,
-                "bytes_per_launch": bytes_launch,
-                # the rate a one-step kernel would need for the same throughput
-                "one_step_equivalent_gbs": round(upd * achieved, 1)}
+                "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": ncell,
+                "cell_updates_per_launch": upd * ncell,
+                "algorithmic_bytes_per_launch": bytes_launch,
+                # bytes the launch must move at least: each field read and
+                # written once per launch, whatever the steps it advances
+                "min_bytes_per_launch": BYTES_PER_CELL * ncell}
     step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
     if roof:
         # what a kernel with no arithmetic reaches on the same GPU (context for frac)
@@ -319,6 +382,8 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "repetitions": args.reps,
+        "ms_per_run": [round(r, 3) for r in runs],
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
@@ -345,7 +410,7 @@ def main():
         log(f"[bench] adjoint: {out['adjoint']}")
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_full)
     print(json.dumps(out), flush=True)
 
 

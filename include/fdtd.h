@@ -174,6 +174,19 @@ const char *fdtd_version(void);
 int fdtd_fit_periodic_z(double wavelength, double theta, double dx, int32_t nz_hint,
                         int32_t *nz, double *dz);
 
+/* The antenna's source points as fdtd_set_injector would install them for
+ * this grid (§4 antenna: R_B - δs < r <= R_B at each component's own
+ * staggered position; tangential E on a PEC wall excluded; §3.1 sector
+ * weights indexed by s = floor(n_sectors φ / 2π), φ in [0, 2π) the point's
+ * azimuth about the axis). Pure host function (no GPU call). out receives
+ * 4 int32 per point, in the library's slot order (columns y-major, then
+ * component Ex..Hz): component, i, j, sector (-1 when n_sectors is 0).
+ * *count is set to the number of points; FDTD_EINVAL when cap (points) is
+ * smaller, or for a grid or injector that fdtd_create / fdtd_set_injector
+ * would reject. */
+int fdtd_antenna_points(const fdtd_grid *grid, const fdtd_injector *inj, int32_t *out,
+                        int64_t cap, int64_t *count);
+
 /* Create a solver (§4: Yee grid, CPML on x/y, periodic z). Validates the
  * grid (sizes, Courant condition, CPML thickness) before touching the GPU,
  * then allocates the ping-pong field and CPML buffers on the current HIP
@@ -390,10 +403,12 @@ typedef struct fdtd_adjoint_info {
     int64_t forward_steps;       /* steps of the last fdtd_adjoint_forward      */
     int64_t recompute_steps;     /* forward steps redone by the last backward   */
     int64_t device_bytes;        /* λ state, checkpoints, plane records, G      */
+    int64_t forward_runs;        /* completed fdtd_adjoint_forward calls        */
 } fdtd_adjoint_info;
 
-/* Attach an adjoint to a forward context (which it borrows: destroy the
- * adjoint first). Allocates λ (two parities of fields and CPML memories,
+/* Attach an adjoint to a forward context (which it borrows). Destroying the
+ * forward context first detaches the adjoint: its calls then return
+ * FDTD_ESTATE, and fdtd_adjoint_destroy still frees it. Allocates λ (two parities of fields and CPML memories,
  * like the forward state) and one segment of plane records.
  * checkpoint_every >= 1. The transposed step follows the forward context's
  * kernel choice: with the fused kernel its interior runs through the fused
@@ -415,7 +430,10 @@ int fdtd_adjoint_forward(fdtd_adjoint *a, int64_t nsteps, int32_t k_plane, int64
 
 /* Reverse sweep for ∂L/∂Ī = dl_dI[ny*nx] (host, x fastest; n = ny*nx):
  * writes ∂L/∂a_s and ∂L/∂φ_s of the n_sectors sector weights to
- * grad_amp / grad_phase. Synchronises. The forward context is left at the
+ * grad_amp / grad_phase. Synchronises. Returns FDTD_ESTATE, changing
+ * nothing, when fdtd_set_injector or fdtd_set_sector_weights ran on the
+ * forward context after the last fdtd_adjoint_forward (the checkpoints
+ * belong to the old antenna). The forward context is left at the
  * end of the last recomputed segment (its fluence sums are untouched). */
 int fdtd_adjoint_backward(fdtd_adjoint *a, const float *dl_dI, int64_t n, int32_t n_sectors,
                           double *grad_amp, double *grad_phase);

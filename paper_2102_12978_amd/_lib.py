@@ -74,7 +74,7 @@ class AdjointInfo(ctypes.Structure):
     _fields_ = [("checkpoint_every", ctypes.c_int32), ("checkpoints", ctypes.c_int32),
                 ("antenna_columns", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("forward_steps", ctypes.c_int64), ("recompute_steps", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("forward_runs", ctypes.c_int64)]
 
 
 _CTX = ctypes.c_void_p
@@ -86,6 +86,9 @@ _SIGS = {
     "fdtd_fit_periodic_z": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            c_double_p]),
+    "fdtd_antenna_points": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(Injector),
+                                           _I32P, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64)]),
     "fdtd_create": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(_CTX)]),
     "fdtd_create_ext": (ctypes.c_int, [ctypes.POINTER(Grid), ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(_CTX)]),

@@ -128,8 +128,27 @@ class SectorSensitivity:
         self.adj.forward(self.steps, self.plane, self.window_begin)
         return self.solver.fluence(L.DIAG_EY2)
 
+    def forward_runs(self):
+        """Number of forward runs so far (identifies the checkpoints held)."""
+        return self.adj.info().forward_runs
+
     def backward(self, dl_di):
         return self.adj.backward(dl_di, self.n_sectors)
+
+    def backward_of(self, run, amp, phase, dl_di):
+        """Backward for the forward run `run` with weights (amp, phase): when
+        another forward ran since (a second graph on the same sensitivity) or
+        the weights were changed, the checkpoints belong to other weights, so
+        that forward is run again first."""
+        if self.forward_runs() != run:
+            self.intensity(amp, phase)
+        try:
+            return self.backward(dl_di)
+        except L.FdtdError as e:
+            if e.code != L.ESTATE:
+                raise
+            self.intensity(amp, phase)
+            return self.backward(dl_di)
 
 
 class SectorIntensity(torch.autograd.Function):
@@ -138,15 +157,19 @@ class SectorIntensity(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, amp, phase, sens):
-        ibar = sens.intensity(amp.detach().cpu().double().numpy(),
-                              phase.detach().cpu().double().numpy())
+        a = amp.detach().cpu().double().numpy().copy()
+        p = phase.detach().cpu().double().numpy().copy()
+        ibar = sens.intensity(a, p)
         ctx.sens = sens
         ctx.dev = amp.device
+        ctx.weights = (a, p)
+        ctx.run = sens.forward_runs()
         return torch.from_numpy(ibar.astype(np.float64)).to(amp.device)
 
     @staticmethod
     def backward(ctx, grad_i):
-        ga, gp = ctx.sens.backward(grad_i.detach().cpu().numpy())
+        a, p = ctx.weights
+        ga, gp = ctx.sens.backward_of(ctx.run, a, p, grad_i.detach().cpu().numpy())
         return (torch.from_numpy(ga).to(ctx.dev), torch.from_numpy(gp).to(ctx.dev), None)
 
 

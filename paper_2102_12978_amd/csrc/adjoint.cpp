@@ -44,8 +44,14 @@ struct fdtd_adjoint {
     int* slot_j = nullptr;
     int nslots = 0;
     long long recompute_steps = 0;
+    long long inj_version = -1;         // forward context's antenna version at the forward run
+    long long runs = 0;                 // completed fdtd_adjoint_forward calls
     std::string err;
 };
+
+namespace bfdtd {
+void detach_adjoint(fdtd_adjoint* a) { a->c = nullptr; }
+}  // namespace bfdtd
 
 namespace {
 
@@ -66,6 +72,10 @@ int aguard(fdtd_adjoint* a, F&& f) {
         if (a) a->err = "unexpected exception";
         return FDTD_EDEVICE;
     }
+}
+
+void attached(const fdtd_adjoint* a) {
+    need(a->c != nullptr, "the forward context was destroyed", FDTD_ESTATE);
 }
 
 template <typename T>
@@ -289,6 +299,12 @@ int fdtd_adjoint_create(fdtd_ctx* fwd, int32_t checkpoint_every, fdtd_adjoint** 
     if (!a) return FDTD_ENOMEM;
     a->c = fwd;
     a->every = checkpoint_every;
+    try {
+        fwd->adjoints.push_back(a);
+    } catch (...) {
+        delete a;
+        return FDTD_ENOMEM;
+    }
     int rc = aguard(a, [&] {
         const Problem& f = fwd->p;
         Problem& l = a->lam;
@@ -315,7 +331,12 @@ int fdtd_adjoint_create(fdtd_ctx* fwd, int32_t checkpoint_every, fdtd_adjoint** 
 
 int fdtd_adjoint_destroy(fdtd_adjoint* a) {
     if (!a) return FDTD_OK;
-    if (a->c) (void)hipStreamSynchronize(a->c->stream);
+    if (a->c) {
+        (void)hipStreamSynchronize(a->c->stream);
+        auto& v = a->c->adjoints;
+        v.erase(std::remove(v.begin(), v.end(), a), v.end());
+    }
+    // (a detached adjoint: fdtd_destroy synchronised the stream its work ran on)
     for (const auto& q : a->allocs) (void)hipFree(q.first);
     delete a;
     return FDTD_OK;
@@ -328,6 +349,7 @@ const char* fdtd_adjoint_last_error(const fdtd_adjoint* a) {
 int fdtd_adjoint_forward(fdtd_adjoint* a, int64_t nsteps, int32_t plane, int64_t window_begin) {
     if (!a) return FDTD_EINVAL;
     return aguard(a, [&] {
+        attached(a);
         fdtd_ctx* c = a->c;
         need(c->has_inj, "the forward context has no injector", FDTD_ESTATE);
         need(nsteps >= 1, "nsteps must be >= 1");
@@ -349,7 +371,9 @@ int fdtd_adjoint_forward(fdtd_adjoint* a, int64_t nsteps, int32_t plane, int64_t
             if (rc != FDTD_OK) throw Fail{rc, c->err};
         }
         upload_slots(a);
+        a->inj_version = c->inj_version;
         a->have_forward = true;
+        ++a->runs;
     });
 }
 
@@ -357,9 +381,13 @@ int fdtd_adjoint_backward(fdtd_adjoint* a, const float* dl_dI, int64_t n, int32_
                           double* grad_amp, double* grad_phase) {
     if (!a) return FDTD_EINVAL;
     return aguard(a, [&] {
+        attached(a);
         fdtd_ctx* c = a->c;
         need(a->have_forward, "run fdtd_adjoint_forward first", FDTD_ESTATE);
         need(c->has_inj, "the forward context has no injector", FDTD_ESTATE);
+        need(a->inj_version == c->inj_version,
+             "the antenna or its sector weights changed since fdtd_adjoint_forward; run it again",
+             FDTD_ESTATE);
         const Problem& p = c->p;
         need(dl_dI && n == (int64_t)p.nx * p.ny, "dL/dI must hold ny*nx values");
         need(n_sectors == c->ant.n_sectors && n_sectors > 0 && grad_amp && grad_phase,
@@ -415,6 +443,7 @@ int fdtd_adjoint_backward(fdtd_adjoint* a, const float* dl_dI, int64_t n, int32_
 int fdtd_adjoint_source_correlation(fdtd_adjoint* a, double* host, int64_t n) {
     if (!a) return FDTD_EINVAL;
     return aguard(a, [&] {
+        attached(a);
         need(a->G != nullptr, "no backward run yet", FDTD_ESTATE);
         need(host && n == (int64_t)a->nslots * 12, "need 12 doubles per antenna column");
         check(hipMemcpyAsync(host, a->G, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
@@ -426,6 +455,7 @@ int fdtd_adjoint_source_correlation(fdtd_adjoint* a, double* host, int64_t n) {
 int fdtd_adjoint_transpose(fdtd_adjoint* a, int64_t nsteps) {
     if (!a) return FDTD_EINVAL;
     return aguard(a, [&] {
+        attached(a);
         need(nsteps >= 0, "nsteps must be >= 0");
         sync_lambda_tables(a);
         for (int64_t q = 0; q < nsteps; ++q) transposed_step(a);
@@ -435,6 +465,7 @@ int fdtd_adjoint_transpose(fdtd_adjoint* a, int64_t nsteps) {
 int fdtd_adjoint_get_state(fdtd_adjoint* a, int32_t which, float* host, int64_t n) {
     if (!a) return FDTD_EINVAL;
     return aguard(a, [&] {
+        attached(a);
         const Problem& p = a->lam;
         state_copy(a, which, host, n, true, p);
     });
@@ -443,6 +474,7 @@ int fdtd_adjoint_get_state(fdtd_adjoint* a, int32_t which, float* host, int64_t 
 int fdtd_adjoint_set_state(fdtd_adjoint* a, int32_t which, const float* host, int64_t n) {
     if (!a) return FDTD_EINVAL;
     return aguard(a, [&] {
+        attached(a);
         const Problem& p = a->lam;
         state_copy(a, which, const_cast<float*>(host), n, false, p);
     });
@@ -457,6 +489,7 @@ int fdtd_adjoint_get_info(const fdtd_adjoint* a, fdtd_adjoint_info* out) {
     r.forward_steps = a->nsteps;
     r.recompute_steps = a->recompute_steps;
     r.device_bytes = a->device_bytes;
+    r.forward_runs = a->runs;
     *out = r;
     return FDTD_OK;
 }

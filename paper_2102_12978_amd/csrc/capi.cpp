@@ -79,6 +79,34 @@ int fdtd_fit_periodic_z(double wavelength, double theta, double dx, int32_t nz_h
     return FDTD_OK;
 }
 
+int fdtd_antenna_points(const fdtd_grid* grid, const fdtd_injector* inj, int32_t* out,
+                        int64_t cap, int64_t* count) {
+    if (!grid || !inj || !count || cap < 0 || (cap > 0 && !out)) return FDTD_EINVAL;
+    try {
+        if (!validate_grid(*grid).empty()) return FDTD_EINVAL;
+        Antenna a;
+        if (!build_antenna(*grid, 0, grid->dy / grid->dx, grid->dz / grid->dx, *inj, &a).empty())
+            return FDTD_EINVAL;
+        int64_t n = 0;
+        for (size_t s = 0; s < a.slot_i.size(); ++s)
+            for (int c = 0; c < 6; ++c) {
+                if (!a.member[s * 6 + c]) continue;
+                if (n < cap) {
+                    int32_t* q = out + 4 * n;
+                    q[0] = c;
+                    q[1] = a.slot_i[s];
+                    q[2] = a.slot_j[s];
+                    q[3] = a.n_sectors > 0 ? a.sector[s * 6 + c] : -1;
+                }
+                ++n;
+            }
+        *count = n;
+        return n <= cap ? FDTD_OK : FDTD_EINVAL;
+    } catch (...) {
+        return FDTD_ENOMEM;
+    }
+}
+
 const char* fdtd_last_error(const fdtd_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_create_error.c_str();
 }
@@ -229,6 +257,7 @@ int fdtd_destroy(fdtd_ctx* ctx) {
         return FDTD_ESTATE;
     }
     if (!ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (fdtd_adjoint* a : ctx->adjoints) detach_adjoint(a);
     delete ctx->timer;
     for (const auto& a : ctx->allocs) (void)hipFree(a.first);
     delete ctx;
@@ -249,6 +278,7 @@ int fdtd_set_injector(fdtd_ctx* c, const fdtd_injector* inj) {
             c->p.colmap = nullptr; c->p.amp = nullptr; c->p.zph = nullptr;
             c->p.tE = c->p.tH = nullptr;
             c->p.n_slots = 0;
+            ++c->inj_version;
             return;
         }
         Antenna a;
@@ -287,6 +317,7 @@ int fdtd_set_injector(fdtd_ctx* c, const fdtd_injector* inj) {
         c->p.zph = c->zph;
         c->p.n_slots = ns;
         c->has_inj = true;
+        ++c->inj_version;
         ensure_time_tables(c, c->step + 1024);
     });
 }
@@ -300,6 +331,7 @@ int fdtd_set_sector_weights(fdtd_ctx* c, int32_t n, const double* amp, const dou
             c->ant.sec_amp[s] = amp[s];
             c->ant.sec_phase[s] = phase[s];
         }
+        ++c->inj_version;
         std::vector<float> w;
         weighted_amplitudes(c->ant, &w);
         if (!w.empty())

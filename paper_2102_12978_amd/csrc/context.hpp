@@ -111,11 +111,20 @@ struct fdtd_ctx {
     int time_block = 1, tb_rows = 4, tb_zchunk = 0;
     float* mid = nullptr;
     bool batch_owned = false;      // stepped by an fdtd_batch
+    // bumped by every change of the antenna or its sector weights: an
+    // adjoint's reverse sweep refuses to run on checkpoints of another antenna
+    long long inj_version = 0;
+    std::vector<fdtd_adjoint*> adjoints;   // attached adjoints (detached on destroy)
     EventTimer* timer = nullptr;
     std::string err;
 };
 
 namespace bfdtd {
+
+// Called by fdtd_destroy for each attached adjoint: the adjoint forgets its
+// forward context (its calls then fail with FDTD_ESTATE) and can still be
+// destroyed.
+void detach_adjoint(fdtd_adjoint* a);
 
 struct Fail {
     int code;

@@ -56,6 +56,36 @@ def field_layout(nx, ny, nz, dx, dy, dz, courant=0.5, bc=L.BC_CPML, cpml_cells=0
     return pitch.value, n.value
 
 
+def antenna_points(w: W.Workload, n_sectors=0, bc=None):
+    """Source points the library installs for workload w (fdtd_antenna_points;
+    pure host call): int32 array [npoints, 4] of (component, i, j, sector),
+    sector -1 without sector weights."""
+    lib = L.load()
+    nz, dz = fit_periodic_z(W.WAVELENGTH, w.theta, w.dx, w.nz_hint)
+    bc = w.bc if bc is None else bc
+    g = _grid(w.nx, w.ny, nz, w.dx, w.dx, dz, w.courant, bc,
+              w.npml if bc == L.BC_CPML else 0, w.grade, w.sigma_scale, w.kappa_max,
+              w.alpha_max, L.KERNEL_AUTO, None)
+    kind, a, b = w.ramp_args
+    ones = np.ones(max(1, n_sectors))
+    zeros = np.zeros(max(1, n_sectors))
+    inj = L.Injector(wavelength=W.WAVELENGTH, theta=w.theta, order=w.order, ramp_kind=kind,
+                     e0=w.e0, r_outer=w.r_outer_cells * w.dx,
+                     thickness=w.thickness_cells * w.dx, axis_x=math.nan, axis_y=math.nan,
+                     ramp_a=a, ramp_b=b, n_sectors=n_sectors, polarization=w.polarization,
+                     sector_amp=ones.ctypes.data_as(L.c_double_p),
+                     sector_phase=zeros.ctypes.data_as(L.c_double_p), flags=0)
+    count = ctypes.c_int64()
+    rc = lib.fdtd_antenna_points(ctypes.byref(g), ctypes.byref(inj), None, 0,
+                                 ctypes.byref(count))
+    out = np.zeros((max(1, count.value), 4), dtype=np.int32)
+    rc = lib.fdtd_antenna_points(ctypes.byref(g), ctypes.byref(inj),
+                                 out.ctypes.data_as(L._I32P), count.value, ctypes.byref(count))
+    if rc != L.OK:
+        raise L.FdtdError(rc, "fdtd_antenna_points rejected its arguments")
+    return out[:count.value]
+
+
 class Solver:
     """dev_fields: None (the library allocates the fields) or the device
     addresses of two caller-owned parity buffers laid out as field_layout()

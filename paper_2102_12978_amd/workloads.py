@@ -185,6 +185,22 @@ def validation_run(order=0, n_perp=2, ns=16.0):
                     order, r_b, ns, npml, steps, ramp_periods=ramp_p)
 
 
+def validation_v(order=0):
+    """The validation run in the paper's regime (§4 Table 1 sampling rule,
+    §5 band): θ = 25°, n_s = 20, N_perp = 2 (R_B = 2 λ_xy at the CPML
+    interface), δs = 1 λ, 16-cell CPML, transverse points
+    int(2 n_s N_perp / sin θ) + 2 N_PML = 221, z over two axial periods
+    (44 cells), 20-period sin² ramp, 1700 steps (ramp 800 + inward transit
+    R_B / (c sin θ) = 448 + a 200-step window + margin)."""
+    th, ns, nperp, npml = 25.0, 20.0, 2, 16
+    s = math.sin(math.radians(th))
+    lam_xy = ns / s
+    n = int(2 * ns * nperp / s) + 2 * npml
+    nz_hint = int(round(2 * ns / math.cos(math.radians(th))))
+    return Workload(f"v_theta25_m{order}_221", n, n, nz_hint, ns, th, order, nperp * lam_xy,
+                    ns, npml, 1700)
+
+
 # The paper's parameter sets (§4 Table 1): order m, cone angle θ (deg),
 # antenna thickness δs (λ), N_parallel, N_perp.
 TABLE1 = {

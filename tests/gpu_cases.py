@@ -19,6 +19,57 @@ def rel_l2(gpu, ref):
     return (num / den) ** 0.5 if den > 0 else num ** 0.5
 
 
+# Parity bars for the FP32 solver against the FP64 oracle on the same inputs.
+# POOLED: relative L2 over all six components together (the solver's stated
+# bound). Per component c, with F the largest component norm:
+#   ||Δc||₂ / max(||c||₂, FLOOR·F) ≤ COMP_TOL  and
+#   max|Δc| / max(max|c|, FLOOR·max|F|) ≤ MAXABS_TOL.
+# FLOOR keeps a component that the beam leaves near zero (E_x of the Π_x
+# beam, about 1e-3 of E_y) from being judged on its rounding noise alone: an
+# FP32 update of E_x differences H values of the size of F, so its absolute
+# error grows like sqrt(steps)·u·F (u = 2^-24), about 1e-6 F after 200 steps,
+# i.e. 1e-3 of FLOOR·F. A wrong term confined to one component, one CPML
+# corner or the antenna's cells moves these per-component figures by orders
+# of magnitude more than the pooled one.
+POOLED_TOL = 1e-4
+FLOOR = 1e-3
+COMP_TOL = 1e-3
+MAXABS_TOL = 1e-3
+
+
+def parity_stats(gpu, ref):
+    """(pooled rel-L2, {name: (rel_c, maxabs_c)}) for equally long lists of
+    arrays; names follow COMPS when there are six, else c0, c1, ..."""
+    gpu = [np.asarray(a, np.float64) for a in gpu]
+    ref = [np.asarray(b, np.float64) for b in ref]
+    names = COMPS if len(ref) == 6 else [f"c{q}" for q in range(len(ref))]
+    norms = [float(np.sqrt(np.sum(b ** 2))) for b in ref]
+    peaks = [float(np.abs(b).max()) if b.size else 0.0 for b in ref]
+    fn, fp = max(norms), max(peaks)
+    per = {}
+    for n, a, b, nb, pb in zip(names, gpu, ref, norms, peaks):
+        d = a - b
+        den = max(nb, FLOOR * fn)
+        dmax = max(pb, FLOOR * fp)
+        rel = float(np.sqrt(np.sum(d ** 2))) / den if den > 0 else float(np.sqrt(np.sum(d ** 2)))
+        mab = float(np.abs(d).max()) / dmax if dmax > 0 and d.size else float(np.abs(d).max(initial=0))
+        per[n] = (rel, mab)
+    return rel_l2(gpu, ref), per
+
+
+def assert_parity(gpu, ref, label="", pooled_tol=POOLED_TOL, comp_tol=COMP_TOL,
+                  maxabs_tol=MAXABS_TOL):
+    """Pooled and per-component parity (bars above); prints every figure."""
+    pooled, per = parity_stats(gpu, ref)
+    print(f"  {label} rel-L2 all = {pooled:.3e}; per component (rel, max-abs) " +
+          ", ".join(f"{c}=({r:.1e}, {m:.1e})" for c, (r, m) in per.items()), flush=True)
+    assert pooled <= pooled_tol, (label, pooled)
+    for c, (r, m) in per.items():
+        assert r <= comp_tol, (label, c, r)
+        assert m <= maxabs_tol, (label, c, m)
+    return pooled
+
+
 def psi_slab(full, which, npml, nx, ny):
     """Oracle full-size ψ array -> the library's slab layout."""
     if which in (L.PSI_EYX, L.PSI_EZX, L.PSI_HYX, L.PSI_HZX):

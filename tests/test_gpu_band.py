@@ -1,14 +1,25 @@
 """The HIP solver against the analytic Bessel beam (paper §5 deviation band).
 
-Gate (the paper's regime, §4 Table 1 geometry scaled down): validation run
-with θ = 30°, n_s = 16, R_B = 2 λ_xy, δs = 1 λ; χ below 3 % at the central
-lobe maxima (two for m ≥ 1, where the third ring sits half a transverse
-period from the antenna) and below 7 % at every maximum inside the antenna,
-the band of §5. Report only (thin 2Δx antennas, outside the paper's
-regime): the 256×256×62 runs of order 0 and 1, and the 768×768×255 order-2
-geometry run long enough (3200 steps) for the beam to fill the centre.
+Gated: the validation run in the paper's regime (§4 Table 1 sampling rule):
+θ = 25°, n_s = 20, R_B = 2 λ_xy at the CPML interface, δs = 1 λ, 16-cell
+CPML, 221×221×44, orders 0, 1 and 2, 1700 steps of a CW beam after a
+20-period sin² ramp, ⟨E_y²⟩ over the last 5 periods. The paper's numbers:
+- χ below 3 % at the maxima of the three central lobes, and below 7 % at
+  every maximum inside the antenna (§5, Fig. 6 and the abstract);
+- the intensity invariant along z within ±2 % (§5, Fig. 5): on planes
+  spread over the box, every central-lobe maximum stays within 2 % of its
+  mean over the planes;
+- E_x, which the antenna never injects, far below E_y: the amplitude ratio
+  sqrt(max⟨E_x²⟩ / max⟨E_y²⟩) over the plane below 1e-3 (§5 says about four
+  orders of magnitude; the bound is one order looser).
+Runs that miss a gate are marked xfail with the measured figure.
+
+Report only (thin 2Δx antennas, outside the paper's regime): the
+256×256×62 runs of order 0 and 1, and the 768×768×255 order-2 geometry run
+long enough (3200 steps) for the beam to fill the centre.
 """
 import json
+import math
 import os
 
 import numpy as np
@@ -21,45 +32,103 @@ from paper_2102_12978_amd.solver import Solver
 
 pytestmark = pytest.mark.gpu
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+BAND = GOLDEN["deviation_band"]
+ZINV = GOLDEN["z_invariance_percent"]["value"]
+EX_AMPLITUDE_RATIO = 1e-3
 
 
-def _run(w, steps=None, window=None):
+def _run(w, steps=None, window=None, plane=None, mask=L.DIAG_EY2 | L.DIAG_EX2):
     steps = w.steps if steps is None else steps
     window = w.window_steps if window is None else window
-    print(f"[gpu case] {w.name}: {steps} steps, window {window}", flush=True)
     s = Solver.from_workload(w, kernel=L.KERNEL_FUSED)
     s.set_workload_injector(w)
-    s.set_diagnostics(s.nz // 2, steps - window, L.DIAG_EY2 | L.DIAG_EX2)
+    k = s.nz // 2 if plane is None else plane
+    print(f"[gpu case] {w.name}: {steps} steps, window {window}, plane {k}", flush=True)
+    s.set_diagnostics(k, steps - window, mask)
     s.step(steps)
-    ey2, ex2, ana, info = s.fluence(L.DIAG_EY2), s.fluence(L.DIAG_EX2), s.analytic_ey2(), s.info()
+    ey2, ana, info = s.fluence(L.DIAG_EY2), s.analytic_ey2(), s.info()
+    ex2 = s.fluence(L.DIAG_EX2) if mask & L.DIAG_EX2 else None
     s.close()
     res = A.lobe_deviation(ey2.astype(np.float64), ana.astype(np.float64), info.kr,
                            w.r_outer_cells - w.thickness_cells)
     print(f"  alpha = {res['alpha']:.4f}; chi % at lobes " +
           ", ".join(f"{100 * c:.2f}" for c in res["chi"]), flush=True)
-    return res, ey2, ex2
+    return res, ey2, ex2, ana, info
+
+
+_V = {}
+
+
+def _validation(m):
+    """Mid-plane run plus runs on planes at 0, 1/4 and 3/4 of the box."""
+    if m not in _V:
+        w = W.validation_v(m)
+        res, ey2, ex2, ana, info = _run(w)
+        planes = {info.nz // 2: ey2}
+        for k in (0, info.nz // 4, 3 * info.nz // 4):
+            planes[k] = _run(w, plane=k, mask=L.DIAG_EY2)[1]
+        _V[m] = (w, res, ey2, ex2, ana, info, planes)
+    return _V[m]
+
+
+def _central_spread(w, ana, info, planes):
+    """Largest deviation (%) of a central-lobe maximum from its mean over the
+    planes, at the maxima of the three central lobes along ±x and ±y."""
+    ny, nx = ana.shape
+    xs, ys, r = A.ey_radius(nx, ny)
+    inside = r < w.r_outer_cells - w.thickness_cells - 2.0
+    worst = 0.0
+    for d in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        for c in A._line_maxima(ana.astype(np.float64), xs, ys, inside, d)[:3]:
+            v = np.array([p[c] for p in planes.values()], dtype=np.float64)
+            worst = max(worst, float(np.abs(v / v.mean() - 1.0).max()))
+    return 100 * worst
+
+
+def _xfail_if(cond, what):
+    if cond:
+        pytest.xfail(what)
 
 
 @pytest.mark.parametrize("m", [0, 1, 2])
-def test_validation_band(m):
-    band = GOLDEN["deviation_band"]
-    res, ey2, ex2 = _run(W.validation_run(m))
-    chi = res["chi"]
-    n_central = 3 if m == 0 else 2
+def test_validation_band_all_lobes(m):
+    w, res, *_ = _validation(m)
+    chi = [100 * c for c in res["chi"]]
     assert res["alpha"] > 0 and len(chi) >= 2
-    assert max(chi[:n_central]) * 100 < band["central_three_lobes_max_percent"], chi
-    assert max(chi) * 100 < band["max_percent"], chi
-    # E_x is never injected and stays far below E_y (§5)
-    assert ex2.max() < 1e-3 * ey2.max()
+    assert max(chi) < BAND["max_percent"], chi
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_band_three_central_lobes(m):
+    w, res, *_ = _validation(m)
+    chi = [100 * c for c in res["chi"]]
+    assert max(chi[:3]) < BAND["central_three_lobes_max_percent"], chi
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_z_invariance(m):
+    w, res, ey2, ex2, ana, info, planes = _validation(m)
+    spread = _central_spread(w, ana, info, planes)
+    print(f"  z spread of the central maxima over planes {sorted(planes)}: {spread:.2f} %",
+          flush=True)
+    assert spread < ZINV, spread
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_ex_far_below_ey(m):
+    w, res, ey2, ex2, *_ = _validation(m)
+    ratio = math.sqrt(float(ex2.max()) / float(ey2.max()))
+    print(f"  amplitude ratio sqrt(max<Ex^2>/max<Ey^2>) = {ratio:.2e}", flush=True)
+    assert ratio < EX_AMPLITUDE_RATIO, ratio
 
 
 @pytest.mark.parametrize("m", [0, 1])
 def test_report_256_grid(m):
-    res, ey2, _ = _run(W.grid256(m))
+    res, ey2, *_ = _run(W.grid256(m))
     assert np.isfinite(ey2).all() and res["alpha"] > 0
 
 
 def test_report_large_grid_long_run():
     w = W.grid768()
-    res, ey2, _ = _run(w, steps=3200, window=5 * 48)
+    res, ey2, *_ = _run(w, steps=3200, window=5 * 48)
     assert np.isfinite(ey2).all() and res["alpha"] > 0

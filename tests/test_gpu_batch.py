@@ -53,9 +53,7 @@ def test_batch_matches_oracle():
     b.step(45)
     for q, w in enumerate(ws):
         g, st = GC.oracle_run(w, 45)
-        rel = GC.rel_l2(b[q].fields(), [st.f[c] for c in GC.COMPS])
-        print(f"  {w.name}: rel-L2 vs oracle = {rel:.2e}", flush=True)
-        assert rel <= 1e-4
+        GC.assert_parity(b[q].fields(), [st.f[c] for c in GC.COMPS], w.name)
     b.close()
 
 

@@ -1,8 +1,10 @@
 """GPU parity: the HIP solver (through the C ABI) against the FP64 oracle.
 
 Tolerance: relative L2 over all six field components ≤ 1e-4 (FP32 solver
-against an FP64 reference on the same seeded inputs); CPML memories are
-compared with the same bound.
+against an FP64 reference on the same seeded inputs), and per component a
+relative L2 and a max-abs bound against the component's own size (with a
+floor; tests/gpu_cases.py states the bars and their derivation); the eight
+CPML memories are compared the same way.
 """
 import math
 
@@ -21,21 +23,13 @@ TOL = 1e-4
 
 
 def _compare(s, st, g, psi=True):
-    gpu = s.fields()
-    ref = [st.f[c] for c in GC.COMPS]
-    rel = GC.rel_l2(gpu, ref)
-    per = {c: GC.rel_l2([a], [b]) for c, a, b in zip(GC.COMPS, gpu, ref)}
-    print(f"  rel-L2 all = {rel:.3e}; per component " +
-          ", ".join(f"{c}={v:.1e}" for c, v in per.items()), flush=True)
-    assert rel <= TOL, per
+    rel = GC.assert_parity(s.fields(), [st.f[c] for c in GC.COMPS], "fields")
     if psi and g.bc == P.BC_CPML:
         gp, rp = [], []
         for which, name in GC.PSI.items():
             gp.append(s.get_state(which))
             rp.append(GC.psi_slab(st.psi[name], which, g.npml, g.nx, g.ny))
-        prel = GC.rel_l2(gp, rp)
-        print(f"  psi rel-L2 = {prel:.3e}", flush=True)
-        assert prel <= TOL
+        GC.assert_parity(gp, rp, "psi")
     return rel
 
 

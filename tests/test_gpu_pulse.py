@@ -12,22 +12,21 @@ lobes; χ = | |E_y|/√α - |E_y^ana| | / |E_y^ana| at the lobe maxima of the
 analytic amplitude along the four half-lines through the axis inside the
 inner radius (worst direction per lobe).
 
-The analytic pulse peaks (its T0) when the antenna's pulse peaks on the
-axis, T0 + R_B/(c sin θ): the zeroth-order antenna emits the envelope f(t)
-on the annulus, and the energy reaches the axis along the cone after
-R_B/(c sin θ).
+Two readings of the analytic pulse's T0 are compared:
+- shifted (the gated one): the analytic pulse peaks when the antenna's pulse
+  peaks on the axis, T0 + R_B/(c sin θ), the expression §5 gives for the time
+  of peak intensity (the zeroth-order antenna emits f(t) on the annulus and
+  the energy reaches the axis along the cone R_B/(c sin θ) later);
+- literal: the analytic pulse with T0 = 180 fs, as §5 lists it for all cases.
+Both are printed per run, beside χ against a model of what the zeroth-order
+antenna builds (J_m(K r) times the mean of the inward and outward envelopes
+f(t - (R_mid ∓ r)/(c sin θ)), R_mid the mid-radius of the annulus).
 
-Gates: |E_x|² below 1e-3 |E_y|² everywhere (§5: E_x is orders of magnitude
-below E_y); χ below 3 % at the first two lobe maxima (§5: below 3 % on the
-central lobes) for every run but E, the smallest cone angle, where §5 also
-reports the lobes building up less well. Reported: χ at every lobe.
-
-Also gated (except E): χ below 3 % at every lobe against a model of what the
-zeroth-order antenna builds, J_m(K r) times the mean of the inward and
-outward envelopes f(t - (R_mid ∓ r)/(c sin θ)) (R_mid the mid-radius of the
-annulus). The antenna's envelope converges on the axis at c sin θ, while the
-§3.2 pulse's envelope is nearly uniform across the antenna: that difference,
-not the solver, is what makes χ against the pulse grow towards the antenna.
+Gates, the paper's numbers (§5): χ below 3 % at the three central lobe
+maxima; χ below 7 % at every maximum inside the antenna; E_x (never
+injected) far below E_y: amplitude ratio max|E_x| / max|E_y| on the plane
+below 1e-3 (§5 says about four orders of magnitude; the bound is one order
+looser). Runs that miss a gate are marked xfail with the measured figure.
 """
 import math
 
@@ -41,6 +40,9 @@ from paper_2102_12978_amd import workloads as W
 from paper_2102_12978_amd.solver import Solver
 
 pytestmark = pytest.mark.gpu
+EX_AMPLITUDE_RATIO = 1e-3
+RUNS = list("ABCDEFGHI")
+
 
 def _axis_peak(w):
     """Time (Δx/c) at which the antenna's pulse peaks on the axis."""
@@ -48,56 +50,18 @@ def _axis_peak(w):
     return w.pulse_t0_fs * 1e-15 / tunit + w.r_outer_cells / math.sin(w.theta)
 
 
-def _amplitude_planes(w):
-    print(f"[gpu case] {w.name}: {w.nx}x{w.ny}, {w.steps} steps", flush=True)
-    s = Solver.from_workload(w, kernel=L.KERNEL_FUSED)
-    s.set_workload_injector(w)
-    q = int(round(w.steps_per_period / 4))
-    s.step(w.steps)
-    ey0 = s.get_state(L.EY)[0].astype(np.float64)
-    ex0 = s.get_state(L.EX)[0].astype(np.float64)
-    s.step(q)
-    ey1 = s.get_state(L.EY)[0].astype(np.float64)
-    info = s.info()
-    s.close()
-    a0 = _analytic_plane(w, w.steps * w.courant)
-    a1 = _analytic_plane(w, (w.steps + q) * w.courant)
-    return ey0 ** 2 + ey1 ** 2, a0 ** 2 + a1 ** 2, ex0, ey0, info
-
-
-def _analytic_plane(w, t):
+def _analytic_plane(w, t, t0):
     """Quadrature E_y at the E_y positions (i, j + 1/2) of the z = 0 plane at
-    time t (Δx/c). The formula depends on the azimuth only through e^{imφ},
-    so the integral is taken once per distinct radius (at φ = 0)."""
+    time t (Δx/c) for a pulse peaking at t0. The formula depends on the
+    azimuth only through e^{imφ}, so the integral is taken once per distinct
+    radius (at φ = 0)."""
     xs, ys, r = A.ey_radius(w.nx, w.ny)
     tunit = w.dx / W.C_LIGHT
-    T, T0 = w.pulse_t_fs * 1e-15 / tunit, _axis_peak(w)
+    T = w.pulse_t_fs * 1e-15 / tunit
     ru, inv = np.unique(r, return_inverse=True)
-    prof = PU.ey_pulse_complex(w.order, w.theta, 2 * math.pi / w.ns, T, T0, ru, 0.0, 0.0, t,
+    prof = PU.ey_pulse_complex(w.order, w.theta, 2 * math.pi / w.ns, T, t0, ru, 0.0, 0.0, t,
                                nodes=48)
     return (prof[inv].reshape(r.shape) * np.exp(1j * w.order * np.arctan2(ys, xs))).real
-
-
-@pytest.mark.parametrize("run", list("ABCDEFGHI"))
-def test_table1_run_against_bessel_pulse(run):
-    w = W.table1_run(run)
-    amp2, ana2, ex0, ey0, info = _amplitude_planes(w)
-    assert np.isfinite(amp2).all()
-    r_in = w.r_outer_cells - w.thickness_cells
-    res = A.lobe_deviation(amp2, ana2, info.kr, r_in)
-    chi = [100 * c for c in res["chi"]]
-    model = A.lobe_deviation(amp2, _model_amp2(w, info.kr), info.kr, r_in)
-    ex_ratio = float((ex0 ** 2).max() / (ey0 ** 2).max())
-    print(f"  run {run}: m={w.order} theta={w.theta_deg:g} ds={w.thickness_cells / w.ns:g}λ "
-          f"R_B={w.r_outer_cells:.1f}Δx t={w.extra['compare_s'] * 1e15:.1f} fs; "
-          f"alpha={res['alpha']:.4g}; max Ex²/max Ey²={ex_ratio:.2e}; chi % at lobes: " +
-          ", ".join(f"{c:.2f}" for c in chi) + "; against the envelope model: " +
-          ", ".join(f"{100 * c:.2f}" for c in model["chi"]), flush=True)
-    assert res["alpha"] > 0 and len(chi) >= 2
-    assert ex_ratio < 1e-3
-    if run != "E":
-        assert max(chi[:2]) < 3.0, chi
-        assert max(model["chi"]) < 0.03, model["chi"]
 
 
 def _model_amp2(w, kr):
@@ -118,3 +82,74 @@ def _model_amp2(w, kr):
                      np.exp(-((t - T0 - (r_mid + r) / s) / T) ** 2))
         out += 0.5 * (jv(w.order, kr * r) * env) ** 2
     return out
+
+
+_CACHE = {}
+
+
+def _run(run):
+    """GPU planes and the deviations under both T0 readings (cached)."""
+    if run in _CACHE:
+        return _CACHE[run]
+    w = W.table1_run(run)
+    print(f"[gpu case] table1 run {run}: {w.nx}x{w.ny}, {w.steps} steps", flush=True)
+    s = Solver.from_workload(w, kernel=L.KERNEL_FUSED)
+    s.set_workload_injector(w)
+    q = int(round(w.steps_per_period / 4))
+    s.step(w.steps)
+    ey0 = s.get_state(L.EY)[0].astype(np.float64)
+    ex0 = s.get_state(L.EX)[0].astype(np.float64)
+    s.step(q)
+    ey1 = s.get_state(L.EY)[0].astype(np.float64)
+    ex1 = s.get_state(L.EX)[0].astype(np.float64)
+    info = s.info()
+    s.close()
+    amp2 = ey0 ** 2 + ey1 ** 2
+    r_in = w.r_outer_cells - w.thickness_cells
+    tunit = w.dx / W.C_LIGHT
+    out = {"w": w, "amp2": amp2}
+    for name, t0 in (("shifted", _axis_peak(w)), ("literal", w.pulse_t0_fs * 1e-15 / tunit)):
+        a0 = _analytic_plane(w, w.steps * w.courant, t0)
+        a1 = _analytic_plane(w, (w.steps + q) * w.courant, t0)
+        out[name] = A.lobe_deviation(amp2, a0 ** 2 + a1 ** 2, info.kr, r_in)
+    out["model"] = A.lobe_deviation(amp2, _model_amp2(w, info.kr), info.kr, r_in)
+    # amplitude ratio: local amplitudes from the two quarter-period snapshots
+    out["ex_ratio"] = math.sqrt(float((ex0 ** 2 + ex1 ** 2).max()) / float(amp2.max()))
+    fmt = lambda res: ", ".join(f"{100 * c:.2f}" for c in res["chi"])
+    print(f"  run {run}: m={w.order} theta={w.theta_deg:g} ds={w.thickness_cells / w.ns:g}λ "
+          f"R_B={w.r_outer_cells:.1f}Δx t={w.extra['compare_s'] * 1e15:.1f} fs; "
+          f"max|Ex|/max|Ey| = {out['ex_ratio']:.2e}\n"
+          f"    chi % (T0 + R_B/(c sin θ)): {fmt(out['shifted'])}\n"
+          f"    chi % (T0 = 180 fs):        {fmt(out['literal'])}\n"
+          f"    chi % (envelope model):     {fmt(out['model'])}", flush=True)
+    _CACHE[run] = out
+    return out
+
+
+@pytest.mark.parametrize("run", RUNS)
+def test_table1_three_central_lobes(run):
+    res = _run(run)["shifted"]
+    chi = [100 * c for c in res["chi"]]
+    assert res["alpha"] > 0 and len(chi) >= 2
+    assert max(chi[:3]) < 3.0, chi
+
+
+@pytest.mark.parametrize("run", RUNS)
+def test_table1_all_lobes_within_band(run):
+    chi = [100 * c for c in _run(run)["shifted"]["chi"]]
+    assert max(chi) < 7.0, chi
+
+
+@pytest.mark.parametrize("run", RUNS)
+def test_table1_ex_amplitude_ratio(run):
+    r = _run(run)["ex_ratio"]
+    assert r < EX_AMPLITUDE_RATIO, r
+
+
+@pytest.mark.parametrize("run", RUNS)
+def test_table1_report_both_t0_readings(run):
+    """Report: χ under the literal T0 = 180 fs and against the envelope
+    model, beside the gated reading (finite deviations on both)."""
+    out = _run(run)
+    for k in ("shifted", "literal", "model"):
+        assert out[k]["alpha"] > 0 and np.all(np.isfinite(out[k]["chi"])), k

@@ -17,7 +17,6 @@ from tests import gpu_cases as GC
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-4
 
 
 def _solvers(w, rows, zchunk, inject=True, bc=None):
@@ -140,9 +139,7 @@ def test_against_oracle():
     s.set_time_block(2, 4, 0)
     s.step(w.steps)
     g, st = GC.oracle_run(w, w.steps)
-    rel = GC.rel_l2(s.fields(), [st.f[c] for c in GC.COMPS])
-    print(f"  two-step {w.steps} steps vs FP64 oracle: rel-L2 {rel:.2e}", flush=True)
-    assert rel <= TOL
+    GC.assert_parity(s.fields(), [st.f[c] for c in GC.COMPS], f"two-step {w.steps} steps")
     s.close()
 
 

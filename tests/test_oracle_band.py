@@ -54,48 +54,57 @@ def lobe_deviation(ey2, g, w, m):
     return alpha, radii, chis
 
 
+_RUNS = {}
+
+
 def run_validation(m, n_perp=2, ns=16.0):
-    w = W.validation_run(m, n_perp, ns)
-    g = cases.oracle_grid(w)
-    ant = P.build_antenna(g, cases.oracle_injector(w))
-    d = Y.Diag(plane=g.nz // 2, window_begin=w.steps - w.window_steps, volume=True)
-    Y.run(g, w.steps, ant, diag=d)
-    return w, g, d
+    key = (m, n_perp, ns)
+    if key not in _RUNS:
+        w = W.validation_run(m, n_perp, ns)
+        g = cases.oracle_grid(w)
+        ant = P.build_antenna(g, cases.oracle_injector(w))
+        d = Y.Diag(plane=g.nz // 2, window_begin=w.steps - w.window_steps, volume=True)
+        Y.run(g, w.steps, ant, diag=d)
+        _RUNS[key] = (w, g, d, lobe_deviation(d.mean("ey2"), g, w, m))
+    return _RUNS[key]
 
 
-def check_band(m, n_central=3):
-    band = GOLDEN["deviation_band"]
-    w, g, d = run_validation(m)
-    alpha, radii, chis = lobe_deviation(d.mean("ey2"), g, w, m)
-    assert alpha > 0
-    assert len(chis) >= 2
-    assert max(chis[:n_central]) * 100 < band["central_three_lobes_max_percent"], chis
-    assert max(chis) * 100 < band["max_percent"], chis
-    # z invariance of the intensity at the first lobe maximum (±2 %, §5)
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_band_all_lobes(m):
+    """Every lobe maximum inside the antenna within the paper's 7 %."""
+    w, g, d, (alpha, radii, chis) = run_validation(m)
+    print(f"  m={m}: chi % " + ", ".join(f"{100 * c:.2f}" for c in chis), flush=True)
+    assert alpha > 0 and len(chis) >= 2
+    assert max(chis) * 100 < GOLDEN["deviation_band"]["max_percent"], chis
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_band_three_central_lobes(m):
+    """The three central lobe maxima within the paper's 3 % (m = 0:
+    0.01, 1.6, 1.1 %; m = 2: 0.4, 1.5 %, two maxima inside the antenna)."""
+    w, g, d, (alpha, radii, chis) = run_validation(m)
+    assert max(chis[:3]) * 100 < GOLDEN["deviation_band"]["central_three_lobes_max_percent"], chis
+
+
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_z_invariance(m):
+    """The intensity at the first lobe maximum stays within ±2 % of its
+    mean over every z plane (§5)."""
+    w, g, d, (alpha, radii, chis) = run_validation(m)
     vol = d.sums["ey2_vol"] / d.count
     ax = g.nx // 2
     jr = int(g.ny / 2 - 0.5)
     col = vol[:, jr, ax + int(round(radii[0]))]
-    spread = (col.max() - col.min()) / col.mean()
+    spread = float(np.abs(col / col.mean() - 1.0).max())
     assert spread * 100 < GOLDEN["z_invariance_percent"]["value"], spread
-    return chis, d
 
 
-def test_validation_band_m0():
-    """m = 0: measured χ = 0.01 %, 1.6 %, 1.1 % at the three central maxima."""
-    chis, d = check_band(0)
-    assert len(chis) == 3
-    # E_x is never injected; it stays orders of magnitude below E_y (§5)
-    assert d.mean("ex2").max() < 1e-3 * d.mean("ey2").max()
-
-
-@pytest.mark.slow
-@pytest.mark.parametrize("m", [1, 2])
-def test_validation_band_higher_orders(m):
-    """m = 1: χ = 0.7 %, 2.0 %, 4.4 %; m = 2: 0.4 %, 1.5 % (R_B = 2 λ_xy).
-
-    With R_B = 2 λ_xy the third ring of m = 1 sits half a transverse period
-    from the antenna, where the paper reports the deviation rising; the 3 %
-    bound is applied to the two inner maxima and 7 % to all of them.
-    """
-    check_band(m, n_central=2)
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_validation_ex_far_below_ey(m):
+    """E_x is never injected (§5: about four orders of magnitude below E_y):
+    the amplitude ratio sqrt(max⟨E_x²⟩ / max⟨E_y²⟩) on the plane stays below
+    1e-3."""
+    w, g, d, _ = run_validation(m)
+    ratio = math.sqrt(float(d.mean("ex2").max()) / float(d.mean("ey2").max()))
+    print(f"  m={m}: amplitude ratio {ratio:.2e}", flush=True)
+    assert ratio < 1e-3, ratio
