@@ -314,26 +314,25 @@ int fdtd_set_tile(fdtd_ctx *ctx, int32_t rows, int32_t zchunk);
 #define FDTD_FRAME_FUSED 1
 int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
 
-/* Steps per pass over the interior (temporal blocking). steps = 1: every
- * step runs the one-step kernels. steps = 2: pairs of steps run one
- * two-step interior kernel (the Yee update of §4 applied twice in registers:
- * each field is read and written once per pair, 24 B per cell-update) over
+/* Steps per pass over the fields (temporal blocking). steps = 1: every
+ * step runs the one-step kernels. steps = 2: pairs of steps run the
+ * two-step kernel over the whole grid (the Yee update of §4 with its CPML
+ * and soft source applied twice in registers: each field and CPML memory
+ * is read and written once per pair, 24 B of fields per cell-update), on
  * tiles of 60 x cells by `rows` (2 or 4) rows marching through z chunks of
- * zchunk planes (0 = the whole z), and the frame around it runs the split
- * kernels in four passes through an intermediate copy of the fields, which
- * this call allocates (six components; freed again by steps = 1). The result
- * is bit-identical to one-step runs. Pairs fall back to single steps for
- * the split kernel choice, the periodic test mode, grids too small for the
- * two-step interior, and while the energy diagnostic is on; an odd last
- * step runs alone. */
+ * zchunk planes (0 = the whole z); tiles free of walls and CPML, tiles at
+ * the x walls, at the y walls and at the corners run as four launches. No
+ * buffer is allocated. The result is bit-identical to one-step runs. Pairs
+ * fall back to single steps for the split kernel choice, the periodic test
+ * mode, and while the energy diagnostic or a plane record is on; an odd
+ * last step runs alone. */
 int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchunk);
 
 /* Time candidate tile shapes and frame choices on the live problem (the state
  * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
- * frames, and, when the grid has room for its interior and the device has
- * the free memory, the two-step kernel (fdtd_set_time_block) at rows {4, 2}
- * x z chunks {nz/8, nz/16, nz/4, whole} (rounded up); trying it allocates
- * the intermediate fields, which are freed again if it loses. Each
+ * frames, and, except in the periodic test mode, the two-step kernel
+ * (fdtd_set_time_block) at rows {4, 2} x z chunks {nz/8, nz/16, nz/4,
+ * whole} (rounded up). Each
  * candidate is timed over at least steps_per_trial steps, and over more
  * until the timed span reaches about 2 ms. One-step trials read what the
  * previous trial wrote, as a run does: they go back and forth between the

@@ -369,7 +369,7 @@ int fdtd_step(fdtd_ctx* c, int64_t nsteps) {
         need(nsteps >= 0, "nsteps must be >= 0");
         ensure_time_tables(c, c->step + nsteps);
         ensure_partials(c);
-        const bool pairs = two_step_rect(c).x1 > 0;
+        const bool pairs = two_step_on(c);
         for (int64_t s = 0; s < nsteps;) {
             if (pairs && nsteps - s >= 2) {
                 launch_pair(c, c->step);
@@ -535,9 +535,12 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->tb_zchunk = c->tb_zchunk;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
-    const Frame f2 = two_step_rect(c);
-    const Frame fr = f2.x1 > 0 ? f2 : interior_of(c);
-    out->interior_cells = (long long)(fr.x1 - fr.x0) * (fr.y1 - fr.y0) * c->p.nz;
+    if (two_step_on(c)) {
+        out->interior_cells = step2_interior_cells(c->p, c->tb_rows);
+    } else {
+        const Frame fr = interior_of(c);
+        out->interior_cells = (long long)(fr.x1 - fr.x0) * (fr.y1 - fr.y0) * c->p.nz;
+    }
     return FDTD_OK;
 }
 
@@ -586,12 +589,6 @@ int fdtd_set_time_block(fdtd_ctx* c, int32_t steps, int32_t rows, int32_t zchunk
         need(steps == 1 || steps == 2, "steps must be 1 or 2");
         need(rows == 2 || rows == 4, "rows must be 2 or 4");
         need(zchunk >= 0 && zchunk <= c->p.nz, "zchunk out of range");
-        if (steps == 2 && !c->mid) c->mid = dalloc<float>(c, 6 * (size_t)c->p.fstride);
-        if (steps == 1 && c->mid) {
-            check(hipStreamSynchronize(c->stream), "sync");
-            dfree(c, c->mid);
-            c->mid = nullptr;
-        }
         c->time_block = steps;
         c->tb_rows = rows;
         c->tb_zchunk = zchunk;
@@ -654,7 +651,6 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             int rows, zchunk, frame, xalign, frame_rows, time_block, tb_rows, tb_zchunk;
             unsigned mask;
             EventTimer* timer;
-            bool had_mid;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             float *sf = nullptr, *sp = nullptr;   // scratch fields / CPML memories
             bool done = false;
@@ -678,17 +674,13 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
                 c->tb_zchunk = tb_zchunk;
                 c->mask = mask;
                 (void)hipStreamSynchronize(c->stream);
-                if (c->mid && !had_mid) {
-                    dfree(c, c->mid);
-                    c->mid = nullptr;
-                }
                 try {
                     ensure_partials(c);
                 } catch (...) {
                 }
             }
         } rs{c, c->rows, c->zchunk, c->frame, c->xalign, c->frame_rows, c->time_block,
-             c->tb_rows, c->tb_zchunk, c->mask, c->timer, c->mid != nullptr};
+             c->tb_rows, c->tb_zchunk, c->mask, c->timer};
         check(hipEventCreate(&rs.e0), "event");
         check(hipEventCreate(&rs.e1), "event");
         const hipEvent_t e0 = rs.e0, e1 = rs.e1;
@@ -782,17 +774,8 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         c->xalign = ba;
         c->frame_rows = bfr;
         ensure_partials(c);
-        // the two-step kernel (per step: half a pair), when the grid has room
-        // for its interior and the device for the intermediate fields
-        const size_t mid_bytes = 6 * (size_t)c->p.fstride * sizeof(float);
-        size_t free_b = 0, total_b = 0;
-        const bool had_mid = rs.had_mid;
-        bool try2 = !c->p.periodic && fused2_interior_rect(c->p, 4).x1 > 0;
-        if (try2 && !had_mid) {
-            try2 = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
-                   free_b > mid_bytes + ((size_t)1 << 30);
-            if (try2) c->mid = dalloc<float>(c, 6 * (size_t)c->p.fstride);
-        }
+        // the two-step kernel (per step: half a pair)
+        const bool try2 = !c->p.periodic;
         int bt = 1, btr = c->tb_rows, btz = c->tb_zchunk;
         if (try2) {
             c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
@@ -825,11 +808,6 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             c->tb_zchunk = btz;
         } else {
             c->time_block = 1;
-            if (c->mid && !had_mid) {
-                check(hipStreamSynchronize(c->stream), "sync");
-                dfree(c, c->mid);
-                c->mid = nullptr;
-            }
         }
         rs.done = true;
         if (best_rows) *best_rows = br;

@@ -106,10 +106,8 @@ struct fdtd_ctx {
     int4* ftiles = nullptr;         // fused frame tiles (0, x0, y0, z chunk)
     int nftiles = 0, ftile_cap = 0, fblocks = 0, fcz = 0, frows = 0;
     bfdtd::Frame ftile_rect{0, 0, 0, 0};
-    // two-step interior kernel (time_block 2) and the frame's intermediate
-    // fields (six components, one parity's layout)
+    // steps per pass over the fields (time_block 2: the two-step kernel)
     int time_block = 1, tb_rows = 4, tb_zchunk = 0;
-    float* mid = nullptr;
     bool batch_owned = false;      // stepped by an fdtd_batch
     // bumped by every change of the antenna or its sector weights: an
     // adjoint's reverse sweep refuses to run on checkpoints of another antenna
@@ -304,57 +302,29 @@ inline hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, 
                               c->timer);
 }
 
-// Pairs of steps go through the two-step interior kernel when it is
-// selected, the fused kernel is in use, the grid has room for its interior,
-// and neither the energy record nor a plane record is wanted.
-inline Frame two_step_rect(const fdtd_ctx* c) {
-    if (c->time_block != 2 || !c->mid || c->kernel == FDTD_KERNEL_SPLIT || c->p.periodic ||
-        (c->mask & FDTD_DIAG_ENERGY) || c->p.rec)
-        return Frame{0, 0, 0, 0};
-    return fused2_interior_rect(c->p, c->tb_rows);
+// Pairs of steps go through the two-step kernel when it is selected, the
+// fused kernel is in use, the walls are not periodic, and neither the energy
+// record nor a plane record is wanted (those need every step's state).
+inline bool two_step_on(const fdtd_ctx* c) {
+    return c->time_block == 2 && c->kernel != FDTD_KERNEL_SPLIT && !c->p.periodic &&
+           !(c->mask & FDTD_DIAG_ENERGY) && !c->p.rec;
 }
 
-// Steps n and n + 1 in one pass over the interior: the two-step kernel
-// reads parity par (buffers A) and writes par ^ 1 (B) inside rectangle R,
-// and leaves in the intermediate buffer C the values of R's edge cells
-// that the frame needs. The frame around R goes through the split kernels
-// in four passes:
-//   E^{n+1}: A -> C;   H^{n+3/2}: A, C -> C (E^{n+1} of R's low edges from
-//   the interior kernel);   E^{n+2}: C -> B (H^{n+3/2} of R's high edges
-//   from the interior kernel);   H^{n+5/2}: C, B -> B (E^{n+2} of R's low
-//   edges, in B, from the interior kernel).
-// The CPML memories go par -> par ^ 1 -> par; the two memory buffers then
-// trade places so that the newest is the one of parity par ^ 1.
+// Steps n and n + 1 in one pass over the whole grid: the two-step kernel
+// reads the fields and CPML memories of parity par and writes those of
+// parity par ^ 1.
 // trial: a timing run that leaves the state alone (it writes only parity
-// par ^ 1, the intermediate buffer and, in place, the par ^ 1 memories; no
-// plane sums, and the step count does not move).
+// par ^ 1; no plane sums, and the step count does not move).
 inline void launch_pair(fdtd_ctx* c, long long n, bool trial = false) {
-    const Frame R = two_step_rect(c);
     const int par = c->parity;
     Problem q = c->p;
     q.plane = c->plane;
     const unsigned dm = trial ? 0u : c->mask & 7u;
     const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
     const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
-    check(launch_fused2_interior(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->mid, c->stream,
-                                 c->timer),
-          "two-step interior launch");
-    const Frame none{0, 0, 0, 0};
-    Problem a = q;
-    a.fbase[par ^ 1] = c->mid;
-    a.diag_mask = m0;
-    check(launch_split_pass(a, n, par, R, none, false, c->stream, c->timer), "frame pass");
-    check(launch_split_pass(a, n, par, R, none, true, c->stream, c->timer), "frame pass");
-    Problem b = q;
-    b.fbase[0] = c->mid;
-    b.fbase[1] = q.fbase[par ^ 1];
-    b.pbase[0] = q.pbase[par ^ 1];
-    b.pbase[1] = trial ? q.pbase[par ^ 1] : q.pbase[par];
-    b.diag_mask = m1;
-    check(launch_split_pass(b, n + 1, 0, R, none, false, c->stream, c->timer), "frame pass");
-    check(launch_split_pass(b, n + 1, 0, R, none, true, c->stream, c->timer), "frame pass");
+    check(launch_step2(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->stream, c->timer),
+          "two-step launch");
     if (trial) return;
-    std::swap(c->p.pbase[0], c->p.pbase[1]);
     c->count += (m0 != 0) + (m1 != 0);
     c->parity ^= 1;
     c->step += 2;

@@ -133,20 +133,16 @@ int split_partial_count(const Problem& p, const Frame& fr);
 hipError_t launch_split_frame(const Problem& p, long long n, int parity, const Frame& fr,
                               double* epart, hipStream_t s, LaunchTimer* timer);
 
-// One E (h_pass false) or H pass of the split kernels over the frame around
-// fr; cells inside nodiag skip the plane accumulation.
-hipError_t launch_split_pass(const Problem& p, long long n, int parity, const Frame& fr,
-                             const Frame& nodiag, bool h_pass, hipStream_t s, LaunchTimer* timer);
-
-// Two-step fused interior kernel (kernels_fused2.hip); rows per wavefront 2
-// or 4. The interior it stores, and one launch advancing it from step n to
-// n + 2 (mask0 / mask1: plane accumulation of steps n and n + 1); mid: the
-// intermediate fields, where it leaves E^{n+1} of the rectangle's low-x /
-// low-y edge cells and H^{n+3/2} of its high-x / high-y edge cells.
-Frame fused2_interior_rect(const Problem& p, int rows);
-hipError_t launch_fused2_interior(const Problem& p, long long n, int parity, int rows, int zchunk,
-                                  int mask0, int mask1, float* mid, hipStream_t s,
-                                  LaunchTimer* timer);
+// Two-step kernel over the whole grid (kernels_step2.hip); rows per
+// wavefront 2 or 4; zchunk 0: the whole z. One call advances fields and CPML
+// memories from parity `parity` at step n to parity ^ 1 at step n + 2
+// (mask0 / mask1: plane accumulation of steps n and n + 1) in four launches
+// (interior, x boundary, y boundary and corner tiles). Not for the periodic
+// test mode.
+hipError_t launch_step2(const Problem& p, long long n, int parity, int rows, int zchunk,
+                        int mask0, int mask1, hipStream_t s, LaunchTimer* timer);
+// Cells (times nz) of the interior-class launch: tiles with no wall or CPML
+long long step2_interior_cells(const Problem& p, int rows);
 
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 

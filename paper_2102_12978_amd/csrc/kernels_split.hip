@@ -80,19 +80,4 @@ hipError_t launch_split_frame(const Problem& p, long long n, int parity, const F
     return hipGetLastError();
 }
 
-hipError_t launch_split_pass(const Problem& p, long long n, int parity, const Frame& fr,
-                             const Frame& nodiag, bool h_pass, hipStream_t s, LaunchTimer* timer) {
-    const long long nc = frame_columns(p, fr);
-    if (nc == 0) return hipSuccess;
-    dim3 grid((unsigned)((nc + BT - 1) / BT), p.nz, 1);
-    if (timer) timer->mark(h_pass ? "frame2_h" : "frame2_e");
-    if (h_pass)
-        hipLaunchKernelGGL(split_h_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, nullptr);
-    else
-        hipLaunchKernelGGL(split_e_kernel, grid, dim3(BT), 0, s, p, n, parity, fr, nc, nullptr,
-                           nodiag);
-    if (timer) timer->mark(nullptr);
-    return hipGetLastError();
-}
-
 }  // namespace bfdtd

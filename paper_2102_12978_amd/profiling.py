@@ -30,9 +30,9 @@ def kernel_sha256_16(path=KERNEL_SRC):
 
 def source_of(kernel):
     """Source file of a kernel (by the name the counters carry): the two-step
-    and one-step interior kernels, or the split frame kernels."""
-    if "fused2" in kernel:
-        return os.path.join(CSRC, "kernels_fused2.hip")
+    kernel, the one-step interior kernel, or the split frame kernels."""
+    if "step2" in kernel:
+        return os.path.join(CSRC, "kernels_step2.hip")
     if "split_" in kernel:
         return os.path.join(CSRC, "kernels_split.hip")
     return os.path.join(CSRC, "kernels_fused.hip")
