@@ -166,6 +166,9 @@ def batch_measure(torch, stream, steps=1000, warmup=20):
         "instances": inf.count, "cells": inf.cells, "steps": steps, "warmup": warmup,
         "value": round(value, 2), "unit": "Gcell-updates/s",
         "ms_per_step": round(ms / steps, 4), "tile_cols": cols, "tile_zchunk": zc,
+        "steps_per_pass": inf.time_block,
+        "two_step_tile": {"rows": inf.tb_rows, "zchunk": inf.tb_zchunk,
+                          "work_items_per_pair": inf.tb_items} if inf.time_block == 2 else None,
         "graph_steps": inf.graph_steps, "work_items": inf.work_items,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -478,6 +478,10 @@ typedef struct fdtd_batch_info {
     int64_t device_bytes;        /* device memory held by batch and instances  */
     int32_t kernel;              /* FDTD_KERNEL_FUSED or FDTD_KERNEL_SPLIT      */
     int32_t reserved;
+    int32_t time_block;          /* steps per pass (2: the two-step kernel)     */
+    int32_t tb_rows;             /* two-step kernel: rows per wavefront         */
+    int32_t tb_zchunk;           /* two-step kernel: z planes per work item     */
+    int32_t tb_items;            /* two-step kernel: work items per pair        */
 } fdtd_batch_info;
 
 /* Create a batch. grids[count] (their stream and kernel fields are ignored:
@@ -521,15 +525,28 @@ int fdtd_batch_set_kernel(fdtd_batch *b, int32_t kernel, int32_t rows);
  * workgroup per column block and plane instead of the persistent grid). */
 int fdtd_batch_set_tile(fdtd_batch *b, int32_t cols, int32_t zchunk);
 
+/* Steps per pass (temporal blocking), as fdtd_set_time_block for a single
+ * context: steps = 2 runs pairs of steps of every instance through the
+ * two-step kernel over each whole grid (walls and CPML included; four
+ * launches per pair, one per tile class, over work items (instance, 60-cell
+ * x segment, row group of 4 * rows rows, z chunk of zchunk planes, 0 = the
+ * whole z)); an odd last step runs the step kernel of fdtd_batch_set_kernel.
+ * Bit-identical to one-step runs. rows: 2 or 4. Refused (FDTD_EINVAL) when
+ * an instance is in the periodic test mode. */
+int fdtd_batch_set_time_block(fdtd_batch *b, int32_t steps, int32_t rows, int32_t zchunk);
+
 /* Steps recorded per graph: an even number in [2, 1000], or 0 to launch
  * every step directly. */
 int fdtd_batch_set_graph_steps(fdtd_batch *b, int32_t steps);
 
 /* Time every kernel and work-item shape (fused with zchunk in
  * {0, 32, 16, 8}; split with cols x zchunk in {64, 128, 256} x
- * {0, 16, 8, 4, 1}) for steps_per_trial steps on the live state and keep
- * the fastest; *best_cols is 0 when the fused kernel wins. Trials write only
- * the buffers of the next parity, so the state is unchanged. */
+ * {0, 16, 8, 4, 1}; and, without periodic instances, the two-step kernel at
+ * rows {2, 4} x zchunk {16, 32, 8}) for steps_per_trial steps on the live
+ * state and keep the fastest (fdtd_batch_get_info reports whether the
+ * two-step kernel won); *best_cols is 0 when the fused kernel wins among the
+ * one-step kernels, which odd steps use. Trials write only the buffers of
+ * the next parity, so the state is unchanged. */
 int fdtd_batch_autotune(fdtd_batch *b, int32_t steps_per_trial, int32_t *best_cols,
                         int32_t *best_zchunk);
 

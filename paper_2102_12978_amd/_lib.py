@@ -67,7 +67,9 @@ class BatchInfo(ctypes.Structure):
                 ("blocks", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
                 ("cells", ctypes.c_int64), ("step", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("kernel", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("time_block", ctypes.c_int32),
+                ("tb_rows", ctypes.c_int32), ("tb_zchunk", ctypes.c_int32),
+                ("tb_items", ctypes.c_int32)]
 
 
 class AdjointInfo(ctypes.Structure):
@@ -139,6 +141,8 @@ _SIGS = {
     "fdtd_batch_step": (ctypes.c_int, [_BATCH, ctypes.c_int64]),
     "fdtd_batch_set_tile": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_batch_set_graph_steps": (ctypes.c_int, [_BATCH, ctypes.c_int32]),
+    "fdtd_batch_set_time_block": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32,
+                                                 ctypes.c_int32]),
     "fdtd_batch_set_kernel": (ctypes.c_int, [_BATCH, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_batch_autotune": (ctypes.c_int, [_BATCH, ctypes.c_int32, _I32P, _I32P]),
     "fdtd_batch_get_info": (ctypes.c_int, [_BATCH, ctypes.POINTER(BatchInfo)]),

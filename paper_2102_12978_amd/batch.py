@@ -77,6 +77,9 @@ class Batch:
     def set_kernel(self, kernel, rows=2):
         self._c(self._lib.fdtd_batch_set_kernel(self._b, int(kernel), int(rows)))
 
+    def set_time_block(self, steps, rows=2, zchunk=16):
+        self._c(self._lib.fdtd_batch_set_time_block(self._b, int(steps), int(rows), int(zchunk)))
+
     def set_graph_steps(self, steps):
         self._c(self._lib.fdtd_batch_set_graph_steps(self._b, int(steps)))
 

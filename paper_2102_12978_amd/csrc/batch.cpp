@@ -26,6 +26,11 @@ struct fdtd_batch {
     int kernel = FDTD_KERNEL_SPLIT;    // split E/H passes, or fused boundary tiles
     int bnd_rows = 2;                  // rows per fused boundary tile (2 or 4)
     int graph_steps = 20;              // even, so a replay leaves the parity unchanged
+    // two-step kernel (time_block 2): pairs of steps, four tile-class launches
+    int time_block = 1, tb_rows = 2, tb_zchunk = 16;
+    int4* items2 = nullptr;            // the four classes' work items, back to back
+    int nitems2[4] = {0, 0, 0, 0};
+    long long items2_bytes = 0;
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // per starting parity
     int cu_count = 256;
     long long step = 0;
@@ -143,6 +148,44 @@ void upload_problems(fdtd_batch* b, bool force = false) {
                     hipMemcpyHostToDevice), "copy problems");
 }
 
+// Work items of the two-step kernel for the current instances and tile.
+void build_items2(fdtd_batch* b) {
+    std::vector<Problem> ps;
+    for (const fdtd_ctx* c : b->inst) ps.push_back(c->p);
+    for (const Problem& p : ps) need(p.nz < 65536, "z extent too large for the two-step items");
+    std::vector<int4> it[4];
+    step2_batch_items(ps, b->tb_rows, b->tb_zchunk, it);
+    std::vector<int4> all;
+    for (int c = 0; c < 4; ++c) {
+        b->nitems2[c] = (int)it[c].size();
+        all.insert(all.end(), it[c].begin(), it[c].end());
+    }
+    check(hipStreamSynchronize(b->stream), "sync");
+    drop_graphs(b);
+    if (b->items2) {
+        (void)hipFree(b->items2);
+        b->device_bytes -= b->items2_bytes;
+        b->items2 = nullptr;
+        b->items2_bytes = 0;
+    }
+    b->items2_bytes = (long long)(std::max<size_t>(1, all.size()) * sizeof(int4));
+    b->items2 = static_cast<int4*>(balloc(b, (size_t)b->items2_bytes));
+    if (!all.empty())
+        check(hipMemcpy(b->items2, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice),
+              "copy items");
+}
+
+// One pair of steps of every instance through the two-step kernel.
+hipError_t launch_two(const fdtd_batch* b, hipStream_t s, int off, int par, int diag) {
+    const int4* it[4];
+    long long o = 0;
+    for (int c = 0; c < 4; ++c) {
+        it[c] = b->items2 + o;
+        o += b->nitems2[c];
+    }
+    return launch_step2_batch(b->probs, it, b->nitems2, b->tb_rows, b->nctr, off, par, diag, s);
+}
+
 hipError_t launch_pair(const fdtd_batch* b, hipStream_t s, int off, int par, int diag) {
     if (b->kernel == FDTD_KERNEL_FUSED)
         return launch_fused_bnd(b->host_probs[0], b->probs, b->work, b->nwork, b->bnd_rows,
@@ -160,8 +203,13 @@ void capture_graph(fdtd_batch* b, int par) {
     hipGraph_t g = nullptr;
     check(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed), "begin capture");
     hipError_t le = hipSuccess;
-    for (int i = 0; i < b->graph_steps && le == hipSuccess; ++i)
-        le = launch_pair(b, b->capture, i, (par + i) & 1, 1);
+    if (b->time_block == 2) {
+        for (int i = 0; 2 * i < b->graph_steps && le == hipSuccess; ++i)
+            le = launch_two(b, b->capture, 2 * i, (par + i) & 1, 1);
+    } else {
+        for (int i = 0; i < b->graph_steps && le == hipSuccess; ++i)
+            le = launch_pair(b, b->capture, i, (par + i) & 1, 1);
+    }
     if (le == hipSuccess) le = launch_batch_advance(b->nctr, b->graph_steps, b->capture);
     hipError_t ee = hipStreamEndCapture(b->capture, &g);
     check(le, "captured launch");
@@ -251,6 +299,7 @@ int fdtd_batch_destroy(fdtd_batch* b) {
     if (b->probs) (void)hipFree(b->probs);
     if (b->nctr) (void)hipFree(b->nctr);
     if (b->work) (void)hipFree(b->work);
+    if (b->items2) (void)hipFree(b->items2);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     delete b;
     return FDTD_OK;
@@ -281,9 +330,16 @@ int fdtd_batch_step(fdtd_batch* b, int64_t nsteps) {
                 left -= b->graph_steps;
             }
         }
-        for (; left > 0; --left) {
-            check(launch_pair(b, b->stream, 0, b->parity, 1), "batch launch");
-            check(launch_batch_advance(b->nctr, 1, b->stream), "counter advance");
+        for (; left > 0;) {
+            if (b->time_block == 2 && left >= 2) {
+                check(launch_two(b, b->stream, 0, b->parity, 1), "batch launch");
+                check(launch_batch_advance(b->nctr, 2, b->stream), "counter advance");
+                left -= 2;
+            } else {
+                check(launch_pair(b, b->stream, 0, b->parity, 1), "batch launch");
+                check(launch_batch_advance(b->nctr, 1, b->stream), "counter advance");
+                left -= 1;
+            }
             b->parity ^= 1;
         }
         b->step = n0 + nsteps;
@@ -311,6 +367,23 @@ int fdtd_batch_set_kernel(fdtd_batch* b, int32_t kernel, int32_t rows) {
         b->kernel = kernel;
         b->bnd_rows = rows;
         build_work(b);
+    });
+}
+
+int fdtd_batch_set_time_block(fdtd_batch* b, int32_t steps, int32_t rows, int32_t zchunk) {
+    if (!b) return FDTD_EINVAL;
+    return bguard(b, [&] {
+        need(steps == 1 || steps == 2, "steps must be 1 or 2");
+        need(rows == 2 || rows == 4, "rows must be 2 or 4");
+        need(zchunk >= 0, "zchunk must be >= 0");
+        for (const fdtd_ctx* c : b->inst)
+            need(!c->p.periodic, "the two-step kernel does not run the periodic test mode");
+        b->tb_rows = rows;
+        b->tb_zchunk = zchunk;
+        if (steps == 2) build_items2(b);
+        check(hipStreamSynchronize(b->stream), "sync");
+        drop_graphs(b);
+        b->time_block = steps;
     });
 }
 
@@ -367,6 +440,38 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
                 br = cd.rows;
             }
         }
+        // the two-step kernel (per step: half a pair), except for periodic
+        // instances
+        bool periodic = false;
+        for (const fdtd_ctx* c : b->inst) periodic = periodic || c->p.periodic;
+        int bt = 1, btr = b->tb_rows, btz = b->tb_zchunk;
+        if (!periodic) {
+            const int rows0 = b->tb_rows, zc0 = b->tb_zchunk;
+            for (int rows : {2, 4})
+                for (int zc : {16, 32, 8}) {
+                    b->tb_rows = rows;
+                    b->tb_zchunk = zc;
+                    build_items2(b);
+                    check(launch_two(b, b->stream, 0, b->parity, 0), "trial");
+                    const int pairs = std::max(1, steps_per_trial / 2);
+                    check(hipEventRecord(e0, b->stream), "event");
+                    for (int t = 0; t < pairs; ++t)
+                        check(launch_two(b, b->stream, 0, b->parity, 0), "trial");
+                    check(hipEventRecord(e1, b->stream), "event");
+                    check(hipEventSynchronize(e1), "event sync");
+                    float ms = 0.f;
+                    check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+                    ms *= (float)steps_per_trial / (float)(2 * pairs);
+                    if (ms < best) {
+                        best = ms;
+                        bt = 2;
+                        btr = rows;
+                        btz = zc;
+                    }
+                }
+            b->tb_rows = rows0;
+            b->tb_zchunk = zc0;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         b->kernel = bk;
@@ -374,6 +479,10 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
         b->cols = bc;
         b->zchunk = bz;
         build_work(b);
+        b->tb_rows = btr;
+        b->tb_zchunk = btz;
+        if (bt == 2) build_items2(b);
+        b->time_block = bt;
         if (best_cols) *best_cols = bk == FDTD_KERNEL_FUSED ? 0 : bc;
         if (best_zchunk) *best_zchunk = bz;
     });
@@ -396,6 +505,10 @@ int fdtd_batch_get_info(const fdtd_batch* b, fdtd_batch_info* out) {
     r.step = b->step;
     r.device_bytes = bytes;
     r.kernel = b->kernel;
+    r.time_block = b->time_block;
+    r.tb_rows = b->tb_rows;
+    r.tb_zchunk = b->tb_zchunk;
+    r.tb_items = b->nitems2[0] + b->nitems2[1] + b->nitems2[2] + b->nitems2[3];
     *out = r;
     return FDTD_OK;
 }

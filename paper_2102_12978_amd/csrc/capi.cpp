@@ -258,6 +258,7 @@ int fdtd_destroy(fdtd_ctx* ctx) {
     }
     if (!ctx->allocs.empty()) (void)hipStreamSynchronize(ctx->stream);
     for (fdtd_adjoint* a : ctx->adjoints) detach_adjoint(a);
+    destroy_side_streams(ctx);
     delete ctx->timer;
     for (const auto& a : ctx->allocs) (void)hipFree(a.first);
     delete ctx;

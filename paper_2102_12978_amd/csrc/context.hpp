@@ -108,6 +108,8 @@ struct fdtd_ctx {
     bfdtd::Frame ftile_rect{0, 0, 0, 0};
     // steps per pass over the fields (time_block 2: the two-step kernel)
     int time_block = 1, tb_rows = 4, tb_zchunk = 0;
+    bfdtd::SideStreams side{};     // the two-step kernel's boundary launches
+    bool side_ok = false;
     bool batch_owned = false;      // stepped by an fdtd_batch
     // bumped by every change of the antenna or its sector weights: an
     // adjoint's reverse sweep refuses to run on checkpoints of another antenna
@@ -315,6 +317,28 @@ inline bool two_step_on(const fdtd_ctx* c) {
 // parity par ^ 1.
 // trial: a timing run that leaves the state alone (it writes only parity
 // par ^ 1; no plane sums, and the step count does not move).
+inline void ensure_side_streams(fdtd_ctx* c) {
+    if (c->side_ok) return;
+    SideStreams& q = c->side;
+    for (int i = 0; i < 3; ++i) {
+        check(hipStreamCreateWithFlags(&q.s[i], hipStreamNonBlocking), "side stream");
+        check(hipEventCreateWithFlags(&q.join[i], hipEventDisableTiming), "side event");
+    }
+    check(hipEventCreateWithFlags(&q.fork, hipEventDisableTiming), "side event");
+    c->side_ok = true;
+}
+
+inline void destroy_side_streams(fdtd_ctx* c) {
+    if (!c->side_ok) return;
+    for (int i = 0; i < 3; ++i) {
+        if (c->side.s[i]) (void)hipStreamDestroy(c->side.s[i]);
+        if (c->side.join[i]) (void)hipEventDestroy(c->side.join[i]);
+    }
+    if (c->side.fork) (void)hipEventDestroy(c->side.fork);
+    c->side = SideStreams{};
+    c->side_ok = false;
+}
+
 inline void launch_pair(fdtd_ctx* c, long long n, bool trial = false) {
     const int par = c->parity;
     Problem q = c->p;
@@ -322,7 +346,9 @@ inline void launch_pair(fdtd_ctx* c, long long n, bool trial = false) {
     const unsigned dm = trial ? 0u : c->mask & 7u;
     const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
     const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
-    check(launch_step2(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->stream, c->timer),
+    ensure_side_streams(c);
+    check(launch_step2(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->stream, c->timer,
+                       &c->side),
           "two-step launch");
     if (trial) return;
     c->count += (m0 != 0) + (m1 != 0);

@@ -137,12 +137,28 @@ hipError_t launch_split_frame(const Problem& p, long long n, int parity, const F
 // wavefront 2 or 4; zchunk 0: the whole z. One call advances fields and CPML
 // memories from parity `parity` at step n to parity ^ 1 at step n + 2
 // (mask0 / mask1: plane accumulation of steps n and n + 1) in four launches
-// (interior, x boundary, y boundary and corner tiles). Not for the periodic
-// test mode.
+// (interior, x boundary, y boundary and corner tiles), the boundary ones on
+// the side streams when given (and no timer is attached). Not for the
+// periodic test mode.
+struct SideStreams {
+    hipStream_t s[3];               // default-priority streams beside the caller's
+    hipEvent_t fork, join[3];       // timing-disabled events
+};
 hipError_t launch_step2(const Problem& p, long long n, int parity, int rows, int zchunk,
-                        int mask0, int mask1, hipStream_t s, LaunchTimer* timer);
+                        int mask0, int mask1, hipStream_t s, LaunchTimer* timer,
+                        const SideStreams* side);
 // Cells (times nz) of the interior-class launch: tiles with no wall or CPML
 long long step2_interior_cells(const Problem& p, int rows);
+// The two-step kernel over many instances: work items (instance, segment,
+// row group, kb | ke << 16) per tile class (0 interior, 1 x boundary, 2 y
+// boundary, 3 corner; nz < 65536), and one pair of steps of every instance
+// (four launches on s, step index *nctr + off, parity par; diag: plane
+// accumulation as each Problem selects from its window on).
+void step2_batch_items(const std::vector<Problem>& probs, int rows, int zchunk,
+                       std::vector<int4> items[4]);
+hipError_t launch_step2_batch(const Problem* probs, const int4* const items[4],
+                              const int nitems[4], int rows, const long long* nctr, int off,
+                              int par, int diag, hipStream_t s);
 
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 

@@ -5,6 +5,10 @@
 
 #include "fdtd_internal.hpp"
 
+// Automatic contraction off for every file that includes this header (the
+// kernels): fused multiply-adds only where the helpers below ask for them.
+#pragma clang fp contract(off)
+
 namespace bfdtd {
 
 // Every pointer in a Problem addresses device global memory. A Problem read
@@ -60,11 +64,35 @@ __device__ __forceinline__ gptr<const float> cy_tab(const Problem& p, int t) {
     return G(p.ctab) + (size_t)6 * p.nx + (size_t)t * p.ny;
 }
 
+// The terms of the cell updates, each with its roundings fixed by an explicit
+// fused multiply-add. Every Yee kernel (one-step, two-step, frame, batch)
+// forms a cell from these, in files compiled with automatic contraction
+// off, so that all of them round a cell alike and their states agree bit
+// for bit whatever the compiler would otherwise fuse.
+//   a·x − b·y      (a curl pair: S_d Δ_d u − S_e Δ_e v)
+__device__ __forceinline__ float curl_pair(float a, float x, float b, float y) {
+    return __builtin_fmaf(a, x, -(b * y));
+}
+//   b·ψ + c·Δ      (CPML memory update)
+__device__ __forceinline__ float cpml_mem(float b, float psi, float c, float d) {
+    return __builtin_fmaf(b, psi, c * d);
+}
+//   k·Δ + ψ        (stretched difference: Δ/κ + ψ)
+__device__ __forceinline__ float stretched(float kinv, float d, float psi) {
+    return __builtin_fmaf(kinv, d, psi);
+}
+//   acc + v²       (plane and energy sums, FP64)
+__device__ __forceinline__ double sq_acc(double acc, float v) {
+    return __builtin_fma((double)v, (double)v, acc);
+}
+
 // Re{a · b}
-__device__ __forceinline__ float cmul_re(float2 a, float2 b) { return a.x * b.x - a.y * b.y; }
+__device__ __forceinline__ float cmul_re(float2 a, float2 b) {
+    return __builtin_fmaf(a.x, b.x, -(a.y * b.y));
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 
 // Column c of the frame -> (x, y). A plane holds fewer than 2^31 cells (the

@@ -121,11 +121,11 @@ __device__ __forceinline__ void e_plane(const Problem& p, int lane, long long n,
             if (r < TY) hz_im = hzl[r];
         }
         // E_x += S_y Δ_y H_z - S_z Δ_z H_y
-        ex[r] += p.sy * (hz[r + 1] - hz[r]) - p.sz * (hy[r] - hym[r]);
+        ex[r] += curl_pair(p.sy, hz[r + 1] - hz[r], p.sz, hy[r] - hym[r]);
         // E_z += S_x Δ_x H_y - S_y Δ_y H_x
-        ez[r] += p.sx * (hy[r] - hy_im) - p.sy * (hx[r + 1] - hx[r]);
+        ez[r] += curl_pair(p.sx, hy[r] - hy_im, p.sy, hx[r + 1] - hx[r]);
         // E_y += S_z Δ_z H_x - S_x Δ_x H_z
-        if (r < TY) ey[r] += p.sz * (hx[r + 1] - hxm[r < TY ? r : 0]) - p.sx * (hz[r + 1] - hz_im);
+        if (r < TY) ey[r] += curl_pair(p.sz, hx[r + 1] - hxm[r < TY ? r : 0], p.sx, hz[r + 1] - hz_im);
         if (slot[r] >= 0) {
             const float2* a = p.amp + (size_t)slot[r] * 6;
             ex[r] += cmul_re(a[EX], pt0);
@@ -195,9 +195,9 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, long long n, int 
         // same association as e_plane (E + (curl)), so the column matches the
         // value its own segment forms bit for bit
         float vy = bcast(g, Hq::R_EY + r);
-        vy += p.sz * (hxr - hxkm[r]) - p.sx * (bcast(g, Hq::R_HZ + r) - hz[r + 1]);
+        vy += curl_pair(p.sz, hxr - hxkm[r], p.sx, bcast(g, Hq::R_HZ + r) - hz[r + 1]);
         float vz = bcast(g, Hq::R_EZ + r);
-        vz += p.sx * (bcast(g, Hq::R_HY + r) - hy[r]) - p.sy * (hxr - hx_prev);
+        vz += curl_pair(p.sx, bcast(g, Hq::R_HY + r) - hy[r], p.sy, hxr - hx_prev);
         if (slot_h[r] >= 0) {
             const float2* a = p.amp + (size_t)slot_h[r] * 6;
             vy += cmul_re(a[EY], pt0);
@@ -272,9 +272,9 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
             if (epart_slot) en += (double)ex[r] * ex[r] + (double)ey[r] * ey[r] + (double)ez[r] * ez[r];
             if (kk == p.plane) {
                 const size_t pl = (size_t)(j0 + r) * nx + T.x, ps = (size_t)nx * ny;
-                if (p.diag_mask & FDTD_DIAG_EX2) p.fl[pl] += (double)ex[r] * ex[r];
-                if (p.diag_mask & FDTD_DIAG_EY2) p.fl[ps + pl] += (double)ey[r] * ey[r];
-                if (p.diag_mask & FDTD_DIAG_EZ2) p.fl[2 * ps + pl] += (double)ez[r] * ez[r];
+                if (p.diag_mask & FDTD_DIAG_EX2) p.fl[pl] = sq_acc(p.fl[pl], ex[r]);
+                if (p.diag_mask & FDTD_DIAG_EY2) p.fl[ps + pl] = sq_acc(p.fl[ps + pl], ey[r]);
+                if (p.diag_mask & FDTD_DIAG_EZ2) p.fl[2 * ps + pl] = sq_acc(p.fl[2 * ps + pl], ez[r]);
                 if (p.rec) p.rec[(size_t)(n - p.rec_begin) * ps + pl] = ey[r];
             }
         }
@@ -353,11 +353,11 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
                 ez_ip = ezh[r];
             }
             // H_x -= S_y Δ_y E_z - S_z Δ_z E_y
-            float vx = hcx[r] - (p.sy * (ecz[r + 1] - ecz[r]) - p.sz * (eny[r] - ecy[r]));
+            float vx = hcx[r] - (curl_pair(p.sy, ecz[r + 1] - ecz[r], p.sz, eny[r] - ecy[r]));
             // H_y -= S_z Δ_z E_x - S_x Δ_x E_z
-            float vy = hcy[r] - (p.sz * (enx[r] - ecx[r]) - p.sx * (ez_ip - ecz[r]));
+            float vy = hcy[r] - (curl_pair(p.sz, enx[r] - ecx[r], p.sx, ez_ip - ecz[r]));
             // H_z -= S_x Δ_x E_y - S_y Δ_y E_x
-            float vz = hcz[r] - (p.sx * (ey_ip - ecy[r]) - p.sy * (ecx[r + 1] - ecx[r]));
+            float vz = hcz[r] - (curl_pair(p.sx, ey_ip - ecy[r], p.sy, ecx[r + 1] - ecx[r]));
             if (slot[r] >= 0) {
                 const float2* a = p.amp + (size_t)slot[r] * 6;
                 vx += cmul_re(a[HX], qt1);

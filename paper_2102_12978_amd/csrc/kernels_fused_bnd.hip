@@ -242,9 +242,9 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
                 if (kk == p.plane) {
                     const size_t pl = (size_t)(j0 + r) * nx + x, ps = (size_t)nx * ny;
                     const gptr<double> fl = G(p.fl);
-                    if (mask & FDTD_DIAG_EX2) fl[pl] += (double)ex[r] * ex[r];
-                    if (mask & FDTD_DIAG_EY2) fl[ps + pl] += (double)ey[r] * ey[r];
-                    if (mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] += (double)ez[r] * ez[r];
+                    if (mask & FDTD_DIAG_EX2) fl[pl] = sq_acc(fl[pl], ex[r]);
+                    if (mask & FDTD_DIAG_EY2) fl[ps + pl] = sq_acc(fl[ps + pl], ey[r]);
+                    if (mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] = sq_acc(fl[2 * ps + pl], ez[r]);
                     if (p.rec) G(p.rec)[(size_t)(n - p.rec_begin) * ps + pl] = ey[r];
                 }
             }

@@ -40,6 +40,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "kernels_common.hpp"
 
@@ -94,21 +95,18 @@ struct Coef {
     float b, c, k;
 };
 
+// Waves per SIMD asked of the register allocator (at least).
 template <int TY, bool XB, bool YB>
-__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2)))
-step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int mask0,
-             int mask1) {
-    // ---- which tile: hardware block b runs on XCD b % 8 ----------------
-    const int nsl = span_count(L.seg), ngl = span_count(L.grp);
-    const int ntile = nsl * ngl;
-    const int lb = (blockIdx.x % 8) * (nblocks_padded / 8) + blockIdx.x / 8;
-    if (lb >= ntile * L.ncz) return;
+constexpr int step2_waves() {
+    return 2;
+}
+
+// One tile: x segment seg, row group grp, planes [kb, ke) of problem p,
+// advanced from step n (parity par) to n + 2.
+template <int TY, bool XB, bool YB>
+__device__ __forceinline__ void step2_tile(const Problem& p, long long n, int par, int seg,
+                                           int grp, int kb, int ke, int mask0, int mask1) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int t = lb % ntile;
-    const int seg = span_at(L.seg, t % nsl);
-    const int grp = span_at(L.grp, t / nsl);
-    const int kb = (lb / ntile) * L.cz;
-    const int ke = min(kb + L.cz, p.nz);
     const int nz = p.nz, nx = p.nx, ny = p.ny;
     const int j0 = (grp * WAVES + w) * TY;
     if (j0 >= ny) {                                            // uniform per wavefront
@@ -122,6 +120,11 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     const bool own = x >= own_lo && x < own_hi;
     const bool inb = !XB || (x >= 0 && x < nx);                // a grid cell
     const bool hold_x = XB && x == 0;                          // E_y, E_z on the x = 0 wall
+    // A lane outside the grid reads the nearest cell of its row instead (so
+    // every load of a row is unconditional): its values feed only cells
+    // outside the grid or held on the wall, and E outside is zeroed after
+    // every E update.
+    const int xc = XB ? min(max(x, 0), nx - 1) : x;
     // rows: inside the grid, and on the y = 0 wall (uniform per row)
     auto row_ok = [&](int r) { return !YB || (j0 + r >= 0 && j0 + r < ny); };
     auto hold_y = [&](int r) { return YB && j0 + r == 0; };
@@ -136,10 +139,10 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
         return (size_t)c * fs + (size_t)kk * plane + (size_t)(long long)(j0 + r) * p.pitch +
                (size_t)(long long)x0;
     };
-    const unsigned lo4 = 4u * (unsigned)lane;
+    const unsigned lo4 = 4u * (unsigned)(xc - x0);
     auto ld = [&](int c, int kk, int r) {
         float v = 0.f;
-        if (row_ok(r) && inb) v = *(gptr<const float>)(uniform(fo + base(c, kk, r)) + lo4);
+        if (row_ok(r)) v = *(gptr<const float>)(uniform(fo + base(c, kk, r)) + lo4);
         return v;
     };
     // plain stores: a tile stores 60 cells of a row, so lines at tile edges
@@ -181,7 +184,7 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     const gptr<float> pw = G(p.pbase[par ^ 1]);
     auto xq = [&](int kk, int r) { return ((size_t)kk * ny + (j0 + r)) * (2 * npml) + xsl; };
     auto yq = [&](int kk, int r) {
-        return ((size_t)kk * (2 * npml) + ysl(r)) * p.pitch + x;
+        return ((size_t)kk * (2 * npml) + ysl(r)) * p.pitch + xc;
     };
     auto ldx = [&](int q, int kk, int r) {   // x-slab memory q (slab lanes only)
         float v = 0.f;
@@ -191,7 +194,7 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     auto stx = [&](int q, int kk, int r, float v) { pw[psi_offset(p, q) + xq(kk, r)] = v; };
     auto ldy = [&](int q, int kk, int r) {   // y-slab memory q (slab rows only)
         float v = 0.f;
-        if (ysl(r) >= 0 && inb) v = po[psi_offset(p, q) + yq(kk, r)];
+        if (ysl(r) >= 0) v = po[psi_offset(p, q) + yq(kk, r)];
         return v;
     };
     auto sty = [&](int q, int kk, int r, float v) { pw[psi_offset(p, q) + yq(kk, r)] = v; };
@@ -201,7 +204,11 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     int slot[TY + 4];
 #pragma unroll
     for (int r = -1; r <= TY + 1; ++r)
-        slot[O + r] = src && row_ok(r) && inb ? G(p.colmap)[(size_t)(j0 + r) * nx + x] : -1;
+    {
+        int v = -1;
+        if (src && row_ok(r)) v = G(p.colmap)[(size_t)(j0 + r) * nx + xc];
+        slot[O + r] = inb ? v : -1;
+    }
     const gptr<const float2> amp = G(p.amp);
     const float2 tE0 = src ? ld2(G(p.tE), n) : make_float2(0.f, 0.f);
     const float2 tE1 = src ? ld2(G(p.tE), n + 1) : make_float2(0.f, 0.f);
@@ -219,9 +226,9 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     const gptr<double> fl = G(p.fl);
     auto accumulate = [&](int mask, int r, float vx, float vy, float vz) {
         const size_t pl = (size_t)(j0 + r) * nx + x, ps = (size_t)nx * ny;
-        if (mask & FDTD_DIAG_EX2) fl[pl] += (double)vx * vx;
-        if (mask & FDTD_DIAG_EY2) fl[ps + pl] += (double)vy * vy;
-        if (mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] += (double)vz * vz;
+        if (mask & FDTD_DIAG_EX2) fl[pl] = sq_acc(fl[pl], vx);
+        if (mask & FDTD_DIAG_EY2) fl[ps + pl] = sq_acc(fl[ps + pl], vy);
+        if (mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] = sq_acc(fl[2 * ps + pl], vz);
     };
     // stored rows: inside the grid (uniform)
     auto row_st = [&](int r) { return j0 + r < ny; };
@@ -235,49 +242,49 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
         const bool hy0 = hold_y(r);
         float tx_hz = d_xhz, tx_hy = d_xhy, ty_hz = d_yhz, ty_hx = d_yhx;
         if constexpr (XB) {
-            const float a = ex_c.b * pyx + ex_c.c * d_xhz;
-            const float b2 = ex_c.b * pzx + ex_c.c * d_xhy;
+            const float a = cpml_mem(ex_c.b, pyx, ex_c.c, d_xhz);
+            const float b2 = cpml_mem(ex_c.b, pzx, ex_c.c, d_xhy);
             if (!hold_x) pyx = a;
             if (!hold_x && !hy0) pzx = b2;
-            tx_hz = ex_c.k * d_xhz + pyx;
-            tx_hy = ex_c.k * d_xhy + pzx;
+            tx_hz = stretched(ex_c.k, d_xhz, pyx);
+            tx_hy = stretched(ex_c.k, d_xhy, pzx);
         }
         if constexpr (YB) {
             if (ysl(r) >= 0) {
                 const Coef cy = eyc[O + r];
-                if (!hy0) pxy = cy.b * pxy + cy.c * d_yhz;
-                const float b2 = cy.b * pzy + cy.c * d_yhx;
+                if (!hy0) pxy = cpml_mem(cy.b, pxy, cy.c, d_yhz);
+                const float b2 = cpml_mem(cy.b, pzy, cy.c, d_yhx);
                 if (!hy0 && !hold_x) pzy = b2;
-                ty_hz = cy.k * d_yhz + pxy;
-                ty_hx = cy.k * d_yhx + pzy;
+                ty_hz = stretched(cy.k, d_yhz, pxy);
+                ty_hx = stretched(cy.k, d_yhx, pzy);
             }
         }
-        if (!hy0) vx += p.sy * ty_hz - p.sz * d_zhy;
-        if (do_y && !hold_x) vy += p.sz * d_zhx - p.sx * tx_hz;
-        if (!hold_x && !hy0) vz += p.sx * tx_hy - p.sy * ty_hx;
+        if (!hy0) vx += curl_pair(p.sy, ty_hz, p.sz, d_zhy);
+        if (do_y && !hold_x) vy += curl_pair(p.sz, d_zhx, p.sx, tx_hz);
+        if (!hold_x && !hy0) vz += curl_pair(p.sx, tx_hy, p.sy, ty_hx);
     };
     auto h_upd = [&](int r, float& vx, float& vy, float& vz, float d_yez, float d_zey,
                      float d_zex, float d_xez, float d_xey, float d_yex, float& pyx, float& pzx,
                      float& pxy, float& pzy, bool do_y) {
         float tx_ez = d_xez, tx_ey = d_xey, ty_ez = d_yez, ty_ex = d_yex;
         if constexpr (XB) {
-            pyx = hx_c.b * pyx + hx_c.c * d_xez;
-            pzx = hx_c.b * pzx + hx_c.c * d_xey;
-            tx_ez = hx_c.k * d_xez + pyx;
-            tx_ey = hx_c.k * d_xey + pzx;
+            pyx = cpml_mem(hx_c.b, pyx, hx_c.c, d_xez);
+            pzx = cpml_mem(hx_c.b, pzx, hx_c.c, d_xey);
+            tx_ez = stretched(hx_c.k, d_xez, pyx);
+            tx_ey = stretched(hx_c.k, d_xey, pzx);
         }
         if constexpr (YB) {
             if (ysl(r) >= 0) {
                 const Coef cy = hyc[O + r];
-                pxy = cy.b * pxy + cy.c * d_yez;
-                pzy = cy.b * pzy + cy.c * d_yex;
-                ty_ez = cy.k * d_yez + pxy;
-                ty_ex = cy.k * d_yex + pzy;
+                pxy = cpml_mem(cy.b, pxy, cy.c, d_yez);
+                pzy = cpml_mem(cy.b, pzy, cy.c, d_yex);
+                ty_ez = stretched(cy.k, d_yez, pxy);
+                ty_ex = stretched(cy.k, d_yex, pzy);
             }
         }
-        vx -= p.sy * ty_ez - p.sz * d_zey;
-        if (do_y) vy -= p.sz * d_zex - p.sx * tx_ez;
-        vz -= p.sx * tx_ey - p.sy * ty_ex;
+        vx -= curl_pair(p.sy, ty_ez, p.sz, d_zey);
+        if (do_y) vy -= curl_pair(p.sz, d_zex, p.sx, tx_ez);
+        vz -= curl_pair(p.sx, tx_ey, p.sy, ty_ex);
     };
     // E beyond the last cell of the grid is zero (the PEC wall)
     auto zero_out = [&](int r, float& vx, float& vy, float& vz) {
@@ -543,6 +550,52 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     }
 }
 
+// Single domain: block b runs on XCD b % 8; blocks are remapped so that
+// each XCD takes a contiguous run of tiles (consecutive segments of a row
+// group and z chunk share halo rows in that XCD's L2).
+template <int TY, bool XB, bool YB>
+__global__ void __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(step2_waves<TY, XB, YB>())))
+step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int mask0,
+             int mask1) {
+    const int nsl = span_count(L.seg), ngl = span_count(L.grp);
+    const int ntile = nsl * ngl;
+    const int lb = (blockIdx.x % 8) * (nblocks_padded / 8) + blockIdx.x / 8;
+    if (lb >= ntile * L.ncz) return;
+    const int t = lb % ntile;
+    const int kb = (lb / ntile) * L.cz;
+    step2_tile<TY, XB, YB>(p, n, par, span_at(L.seg, t % nsl), span_at(L.grp, t / nsl), kb,
+                           min(kb + L.cz, p.nz), mask0, mask1);
+}
+
+// Many instances: one work item per workgroup, (instance, segment, row
+// group, kb | ke << 16), all items of one tile class; the step index comes
+// from a device counter (plus a launch offset) so that a captured graph
+// stays valid when replayed.
+template <int TY, bool XB, bool YB>
+__global__ void __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(step2_waves<TY, XB, YB>())))
+step2_batch_kernel(const Problem* __restrict__ probs, const int4* __restrict__ items,
+                   int nitems, int nblocks_padded, const long long* __restrict__ nctr, int off,
+                   int par, int diag) {
+    const int lb = (blockIdx.x % 8) * (nblocks_padded / 8) + blockIdx.x / 8;
+    if (lb >= nitems) return;
+    // the item is the same for the whole workgroup: keep it, and so the
+    // Problem read with it, in scalar registers
+    const int4 it = items[lb];
+    const int q = __builtin_amdgcn_readfirstlane(it.x);
+    const int seg = __builtin_amdgcn_readfirstlane(it.y);
+    const int grp = __builtin_amdgcn_readfirstlane(it.z);
+    const int kz = __builtin_amdgcn_readfirstlane(it.w);
+    // read in place (restrict: no store of the kernel aliases it); a private
+    // copy indexed by the runtime parity would leave scalar registers
+    const Problem& p = probs[q];
+    const long long n = *nctr + off;
+    const int m0 = diag && p.plane >= 0 && n >= p.win_begin ? p.diag_mask : 0;
+    const int m1 = diag && p.plane >= 0 && n + 1 >= p.win_begin ? p.diag_mask : 0;
+    step2_tile<TY, XB, YB>(p, n, par, seg, grp, kz & 0xffff, kz >> 16, m0, m1);
+}
+
 // Segments and row groups whose tiles form only regular cells (an interval
 // each, possibly empty).
 struct Plan2 {
@@ -595,24 +648,73 @@ hipError_t launch_class(const Problem& p, long long n, int parity, const Launch2
     return e;
 }
 
+// The four classes touch disjoint cells: with side streams (and no
+// per-launch timer) the boundary classes run beside the interior launch,
+// forked from and joined back into s by events.
 template <int TY>
 hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, int mask0,
-                       int mask1, hipStream_t s, LaunchTimer* timer) {
+                       int mask1, hipStream_t s, LaunchTimer* timer, const SideStreams* side) {
     const Plan2 P = plan2(p, TY, zchunk);
     const Span s_int{P.s_lo, P.s_hi, 0, 0}, s_bnd{0, P.s_lo, P.s_hi, P.nseg};
     const Span g_int{P.g_lo, P.g_hi, 0, 0}, g_bnd{0, P.g_lo, P.g_hi, P.ngrp};
+    const bool fork = side && !timer;
+    hipStream_t sx = s, sy = s, sc = s;
     hipError_t e;
-    e = launch_class<TY, false, false>(p, n, parity, Launch2{s_int, g_int, P.cz, P.ncz}, mask0,
-                                       mask1, s, timer, "step2_interior");
-    if (e != hipSuccess) return e;
-    e = launch_class<TY, true, false>(p, n, parity, Launch2{s_bnd, g_int, P.cz, P.ncz}, mask0,
-                                      mask1, s, timer, "step2_xbnd");
-    if (e != hipSuccess) return e;
-    e = launch_class<TY, false, true>(p, n, parity, Launch2{s_int, g_bnd, P.cz, P.ncz}, mask0,
-                                      mask1, s, timer, "step2_ybnd");
-    if (e != hipSuccess) return e;
-    return launch_class<TY, true, true>(p, n, parity, Launch2{s_bnd, g_bnd, P.cz, P.ncz}, mask0,
-                                        mask1, s, timer, "step2_corner");
+    if (fork) {
+        e = hipEventRecord(side->fork, s);
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipStreamWaitEvent(side->s[q], side->fork, 0);
+        if (e != hipSuccess) return e;
+        sx = side->s[0];
+        sy = side->s[1];
+        sc = side->s[2];
+    }
+    e = launch_class<TY, true, true>(p, n, parity, Launch2{s_bnd, g_bnd, P.cz, P.ncz}, mask0,
+                                     mask1, sc, timer, "step2_corner");
+    if (e == hipSuccess)
+        e = launch_class<TY, false, true>(p, n, parity, Launch2{s_int, g_bnd, P.cz, P.ncz}, mask0,
+                                          mask1, sy, timer, "step2_ybnd");
+    if (e == hipSuccess)
+        e = launch_class<TY, true, false>(p, n, parity, Launch2{s_bnd, g_int, P.cz, P.ncz}, mask0,
+                                          mask1, sx, timer, "step2_xbnd");
+    if (e == hipSuccess)
+        e = launch_class<TY, false, false>(p, n, parity, Launch2{s_int, g_int, P.cz, P.ncz}, mask0,
+                                           mask1, s, timer, "step2_interior");
+    if (fork) {
+        for (int q = 0; q < 3; ++q) {
+            hipError_t f = hipEventRecord(side->join[q], side->s[q]);
+            if (f == hipSuccess) f = hipStreamWaitEvent(s, side->join[q], 0);
+            if (e == hipSuccess) e = f;
+        }
+    }
+    return e;
+}
+
+template <int TY, bool XB, bool YB>
+hipError_t launch_batch_class(const Problem* probs, const int4* items, int nitems,
+                              const long long* nctr, int off, int par, int diag, hipStream_t s) {
+    if (nitems <= 0) return hipSuccess;
+    const int nbp = (nitems + 7) / 8 * 8;
+    hipLaunchKernelGGL((step2_batch_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES), 0, s,
+                       probs, items, nitems, nbp, nctr, off, par, diag);
+    return hipGetLastError();
+}
+
+template <int TY>
+hipError_t launch_batch_rows(const Problem* probs, const int4* const items[4],
+                             const int nitems[4], const long long* nctr, int off, int par,
+                             int diag, hipStream_t s) {
+    hipError_t e = launch_batch_class<TY, true, true>(probs, items[3], nitems[3], nctr, off, par,
+                                                      diag, s);
+    if (e == hipSuccess)
+        e = launch_batch_class<TY, false, true>(probs, items[2], nitems[2], nctr, off, par, diag,
+                                                s);
+    if (e == hipSuccess)
+        e = launch_batch_class<TY, true, false>(probs, items[1], nitems[1], nctr, off, par, diag,
+                                                s);
+    if (e == hipSuccess)
+        e = launch_batch_class<TY, false, false>(probs, items[0], nitems[0], nctr, off, par,
+                                                 diag, s);
+    return e;
 }
 
 }  // namespace
@@ -626,10 +728,39 @@ long long step2_interior_cells(const Problem& p, int rows) {
 }
 
 hipError_t launch_step2(const Problem& p, long long n, int parity, int rows, int zchunk,
-                        int mask0, int mask1, hipStream_t s, LaunchTimer* timer) {
+                        int mask0, int mask1, hipStream_t s, LaunchTimer* timer,
+                        const SideStreams* side) {
     if (p.periodic) return hipErrorInvalidValue;
-    if (rows == 2) return launch_rows<2>(p, n, parity, zchunk, mask0, mask1, s, timer);
-    if (rows == 4) return launch_rows<4>(p, n, parity, zchunk, mask0, mask1, s, timer);
+    if (rows == 2) return launch_rows<2>(p, n, parity, zchunk, mask0, mask1, s, timer, side);
+    if (rows == 4) return launch_rows<4>(p, n, parity, zchunk, mask0, mask1, s, timer, side);
+    return hipErrorInvalidValue;
+}
+
+void step2_batch_items(const std::vector<Problem>& probs, int rows, int zchunk,
+                       std::vector<int4> items[4]) {
+    for (int c = 0; c < 4; ++c) items[c].clear();
+    for (int q = 0; q < (int)probs.size(); ++q) {
+        const Problem& p = probs[q];
+        const Plan2 P = plan2(p, rows, zchunk);
+        for (int ch = 0; ch < P.ncz; ++ch) {
+            const int kb = ch * P.cz, ke = std::min(kb + P.cz, p.nz);
+            for (int g = 0; g < P.ngrp; ++g) {
+                const bool gi = g >= P.g_lo && g < P.g_hi;
+                for (int sg = 0; sg < P.nseg; ++sg) {
+                    const bool si = sg >= P.s_lo && sg < P.s_hi;
+                    const int cls = (si ? 0 : 1) + (gi ? 0 : 2);
+                    items[cls].push_back(make_int4(q, sg, g, kb | (ke << 16)));
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_step2_batch(const Problem* probs, const int4* const items[4],
+                              const int nitems[4], int rows, const long long* nctr, int off,
+                              int par, int diag, hipStream_t s) {
+    if (rows == 2) return launch_batch_rows<2>(probs, items, nitems, nctr, off, par, diag, s);
+    if (rows == 4) return launch_batch_rows<4>(probs, items, nitems, nctr, off, par, diag, s);
     return hipErrorInvalidValue;
 }
 

@@ -41,31 +41,31 @@ __device__ __forceinline__ void e_cell(const Problem& p, int par, int i, int j, 
         const float b = cx_tab(p, T_EB)[i], c = cx_tab(p, T_EC)[i], kinv = cx_tab(p, T_EK)[i];
         const size_t q = psix_at(p, k, j, xs);
         float py = pptr(p, par, P_EYX)[q], pz = pptr(p, par, P_EZX)[q];
-        if (!hold_x) py = b * py + c * d_xhz;
-        if (!hold_x && !hold_y) pz = b * pz + c * d_xhy;
+        if (!hold_x) py = cpml_mem(b, py, c, d_xhz);
+        if (!hold_x && !hold_y) pz = cpml_mem(b, pz, c, d_xhy);
         if (store_psi) {
             pptr(p, par ^ 1, P_EYX)[q] = py;
             pptr(p, par ^ 1, P_EZX)[q] = pz;
         }
-        tx_hz = kinv * d_xhz + py;
-        tx_hy = kinv * d_xhy + pz;
+        tx_hz = stretched(kinv, d_xhz, py);
+        tx_hy = stretched(kinv, d_xhy, pz);
     }
     if (ys >= 0) {
         const float b = cy_tab(p, T_EB)[j], c = cy_tab(p, T_EC)[j], kinv = cy_tab(p, T_EK)[j];
         const size_t q = psiy_at(p, k, ys, i);
         float px = pptr(p, par, P_EXY)[q], pz = pptr(p, par, P_EZY)[q];
-        if (!hold_y) px = b * px + c * d_yhz;
-        if (!hold_y && !hold_x) pz = b * pz + c * d_yhx;
+        if (!hold_y) px = cpml_mem(b, px, c, d_yhz);
+        if (!hold_y && !hold_x) pz = cpml_mem(b, pz, c, d_yhx);
         if (store_psi) {
             pptr(p, par ^ 1, P_EXY)[q] = px;
             pptr(p, par ^ 1, P_EZY)[q] = pz;
         }
-        ty_hz = kinv * d_yhz + px;
-        ty_hx = kinv * d_yhx + pz;
+        ty_hz = stretched(kinv, d_yhz, px);
+        ty_hx = stretched(kinv, d_yhx, pz);
     }
-    if (!hold_y) ex += p.sy * ty_hz - p.sz * d_zhy;
-    if (!hold_x) ey += p.sz * d_zhx - p.sx * tx_hz;
-    if (!hold_x && !hold_y) ez += p.sx * tx_hy - p.sy * ty_hx;
+    if (!hold_y) ex += curl_pair(p.sy, ty_hz, p.sz, d_zhy);
+    if (!hold_x) ey += curl_pair(p.sz, d_zhx, p.sx, tx_hz);
+    if (!hold_x && !hold_y) ez += curl_pair(p.sx, tx_hy, p.sy, ty_hx);
     if (slot >= 0) {
         const gptr<const float2> a = G(p.amp) + (size_t)slot * 6;
         ex += cmul_re(ld2(a, EX), pt0);
@@ -98,26 +98,26 @@ __device__ __forceinline__ void h_cell(const Problem& p, int par, int i, int j, 
     if (xs >= 0) {
         const float b = cx_tab(p, T_HB)[i], c = cx_tab(p, T_HC)[i], kinv = cx_tab(p, T_HK)[i];
         const size_t q = psix_at(p, k, j, xs);
-        const float py = b * pptr(p, par, P_HYX)[q] + c * d_xez;
-        const float pz = b * pptr(p, par, P_HZX)[q] + c * d_xey;
+        const float py = cpml_mem(b, pptr(p, par, P_HYX)[q], c, d_xez);
+        const float pz = cpml_mem(b, pptr(p, par, P_HZX)[q], c, d_xey);
         pptr(p, par ^ 1, P_HYX)[q] = py;
         pptr(p, par ^ 1, P_HZX)[q] = pz;
-        tx_ez = kinv * d_xez + py;
-        tx_ey = kinv * d_xey + pz;
+        tx_ez = stretched(kinv, d_xez, py);
+        tx_ey = stretched(kinv, d_xey, pz);
     }
     if (ys >= 0) {
         const float b = cy_tab(p, T_HB)[j], c = cy_tab(p, T_HC)[j], kinv = cy_tab(p, T_HK)[j];
         const size_t q = psiy_at(p, k, ys, i);
-        const float px = b * pptr(p, par, P_HXY)[q] + c * d_yez;
-        const float pz = b * pptr(p, par, P_HZY)[q] + c * d_yex;
+        const float px = cpml_mem(b, pptr(p, par, P_HXY)[q], c, d_yez);
+        const float pz = cpml_mem(b, pptr(p, par, P_HZY)[q], c, d_yex);
         pptr(p, par ^ 1, P_HXY)[q] = px;
         pptr(p, par ^ 1, P_HZY)[q] = pz;
-        ty_ez = kinv * d_yez + px;
-        ty_ex = kinv * d_yex + pz;
+        ty_ez = stretched(kinv, d_yez, px);
+        ty_ex = stretched(kinv, d_yex, pz);
     }
-    hx -= p.sy * ty_ez - p.sz * d_zey;
-    hy -= p.sz * d_zex - p.sx * tx_ez;
-    hz -= p.sx * tx_ey - p.sy * ty_ex;
+    hx -= curl_pair(p.sy, ty_ez, p.sz, d_zey);
+    hy -= curl_pair(p.sz, d_zex, p.sx, tx_ez);
+    hz -= curl_pair(p.sx, tx_ey, p.sy, ty_ex);
     if (slot >= 0) {
         const gptr<const float2> a = G(p.amp) + (size_t)slot * 6;
         hx += cmul_re(ld2(a, HX), qt1);
@@ -168,9 +168,9 @@ __device__ __forceinline__ double e_point(const Problem& p, long long n, int par
     if (k == p.plane && diag_mask) {
         const size_t pl = (size_t)j * p.nx + i, ps = (size_t)p.nx * p.ny;
         const gptr<double> fl = G(p.fl);
-        if (diag_mask & FDTD_DIAG_EX2) fl[pl] += (double)ex * ex;
-        if (diag_mask & FDTD_DIAG_EY2) fl[ps + pl] += (double)ey * ey;
-        if (diag_mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] += (double)ez * ez;
+        if (diag_mask & FDTD_DIAG_EX2) fl[pl] = sq_acc(fl[pl], ex);
+        if (diag_mask & FDTD_DIAG_EY2) fl[ps + pl] = sq_acc(fl[ps + pl], ey);
+        if (diag_mask & FDTD_DIAG_EZ2) fl[2 * ps + pl] = sq_acc(fl[2 * ps + pl], ez);
     }
     if (k == p.plane && p.rec) G(p.rec)[(size_t)(n - p.rec_begin) * p.nx * p.ny + (size_t)j * p.nx + i] = ey;
     return (double)ex * ex + (double)ey * ey + (double)ez * ez;

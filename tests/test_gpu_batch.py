@@ -178,3 +178,42 @@ def test_single_instance_batch_and_step_counts():
     ref, _ = _single(w, 23)
     assert _same(b[0].fields(), ref)
     b.close()
+
+
+@pytest.mark.parametrize("rows,zchunk,graph", [(2, 16, 20), (4, 5, 8), (2, 0, 0)])
+def test_two_step_batch_equals_single_runs(rows, zchunk, graph):
+    """fdtd_batch_set_time_block(2): pairs of steps of every instance run the
+    whole-grid two-step kernel (four tile-class launches per pair, walls and
+    CPML included); graph replays, eager pairs and an odd last step; fields
+    and the plane sums equal the single split runs bit for bit."""
+    ws = W.batch_small()
+    b = Batch(ws)
+    b.set_time_block(2, rows, zchunk)
+    b.set_graph_steps(graph)
+    inf = b.info()
+    print(f"  two-step batch rows={rows} zchunk={zchunk} graph={graph}: "
+          f"{inf.tb_items} work items per pair", flush=True)
+    assert inf.time_block == 2 and inf.tb_items > 0
+    planes = []
+    for q in range(len(ws)):
+        planes.append(b[q].nz // 2)
+        b[q].set_diagnostics(planes[q], 30, L.DIAG_EY2 | L.DIAG_EX2)
+    b.step(21)
+    b.step(24)
+    for q, w in enumerate(ws):
+        ref, (ey2, ex2, count) = _single(w, 45, plane=planes[q], wb=30)
+        assert _same(b[q].fields(), ref), w.name
+        assert b[q].fluence_count() == count == 15
+        assert np.array_equal(b[q].fluence(L.DIAG_EY2), ey2)
+        assert np.array_equal(b[q].fluence(L.DIAG_EX2), ex2)
+    b.close()
+
+
+def test_two_step_batch_refuses_bad_arguments():
+    ws = W.batch_small()[:2]
+    b = Batch(ws)
+    lib = L.load()
+    for args in ((3, 2, 0), (2, 3, 0), (2, 2, -1)):
+        assert lib.fdtd_batch_set_time_block(b._b, *args) == L.EINVAL
+    assert b.info().time_block == 1
+    b.close()
