@@ -262,6 +262,21 @@ int fdtd_set_diagnostics(fdtd_ctx *ctx, int32_t k_plane, int64_t window_begin_st
 /* Advance nsteps leapfrog steps on the context's stream (asynchronous). */
 int fdtd_step(fdtd_ctx *ctx, int64_t nsteps);
 
+/* fdtd_step for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Same steps, kernels
+ * and results (bit for bit) as fdtd_step, but the call allocates, frees and
+ * creates nothing: the energy diagnostic's per-workgroup partial sums go to
+ * a 2 MiB static device array (at most 262,144 partials: FDTD_EINVAL, with
+ * nothing stepped, when a grid and tile need more), the two-step kernel's
+ * boundary launches run on the context's stream after the interior one,
+ * no profiling marks are taken, and the time tables are not grown (steps
+ * past their end: FDTD_ESTATE, nothing stepped; fdtd_set_injector builds
+ * them 1024 steps ahead and fdtd_step grows them). The static array is
+ * shared by every context on a device and keeps the last call's contents
+ * (each energy step clears the part it uses): calls that overlap on one GPU,
+ * from two host threads or on two streams, race. */
+int fdtd_step_static(fdtd_ctx *ctx, int64_t nsteps);
+
 /* Mean over the window of one plane quantity (FDTD_DIAG_EX2, _EY2 or _EZ2),
  * written to host_out[ny*nx] (x fastest). Synchronises. n = capacity.
  * Returns FDTD_EUNSTABLE (after writing host_out) if any sum is NaN or

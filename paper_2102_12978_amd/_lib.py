@@ -104,6 +104,7 @@ _SIGS = {
     "fdtd_set_diagnostics": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int64,
                                             ctypes.c_uint32]),
     "fdtd_step": (ctypes.c_int, [_CTX, ctypes.c_int64]),
+    "fdtd_step_static": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "fdtd_fluence": (ctypes.c_int, [_CTX, ctypes.c_uint32, c_float_p, ctypes.c_int64]),
     "fdtd_fluence_count": (ctypes.c_int, [_CTX, ctypes.POINTER(ctypes.c_int64)]),
     "fdtd_energy": (ctypes.c_int, [_CTX, c_double_p]),

@@ -214,6 +214,10 @@ class Solver:
     def step(self, n=1):
         self._c(self._lib.fdtd_step(self._ctx, int(n)))
 
+    def step_static(self, n=1):
+        """fdtd_step_static: the same steps with no allocation in the call."""
+        self._c(self._lib.fdtd_step_static(self._ctx, int(n)))
+
     def fluence(self, quantity=L.DIAG_EY2):
         out = np.empty((self.ny, self.nx), dtype=np.float32)
         self._c(self._lib.fdtd_fluence(self._ctx, quantity, _fptr(out), out.size))
