@@ -30,6 +30,8 @@ struct fdtd_batch {
     int time_block = 1, tb_rows = 2, tb_zchunk = 16;
     int4* items2 = nullptr;            // the four classes' work items, back to back
     int nitems2[4] = {0, 0, 0, 0};
+    SideStreams side{};                // the boundary classes' launches beside the interior
+    bool side_ok = false;
     long long items2_bytes = 0;
     hipGraphExec_t exec[2] = {nullptr, nullptr};   // per starting parity
     int cu_count = 256;
@@ -183,7 +185,8 @@ hipError_t launch_two(const fdtd_batch* b, hipStream_t s, int off, int par, int 
         it[c] = b->items2 + o;
         o += b->nitems2[c];
     }
-    return launch_step2_batch(b->probs, it, b->nitems2, b->tb_rows, b->nctr, off, par, diag, s);
+    return launch_step2_batch(b->probs, it, b->nitems2, b->tb_rows, b->nctr, off, par, diag, s,
+                              b->side_ok ? &b->side : nullptr);
 }
 
 hipError_t launch_pair(const fdtd_batch* b, hipStream_t s, int off, int par, int diag) {
@@ -255,6 +258,8 @@ int fdtd_batch_create(int32_t count, const fdtd_grid* grids, const fdtd_injector
         check(hipDeviceGetAttribute(&b->cu_count, hipDeviceAttributeMultiprocessorCount, dev),
               "CU count");
         check(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+        create_side_streams(b->side);
+        b->side_ok = true;
         for (int q = 0; q < count; ++q) {
             fdtd_grid g = grids[q];
             g.stream = stream;
@@ -301,6 +306,7 @@ int fdtd_batch_destroy(fdtd_batch* b) {
     if (b->work) (void)hipFree(b->work);
     if (b->items2) (void)hipFree(b->items2);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    release_side_streams(b->side);
     delete b;
     return FDTD_OK;
 }

@@ -317,25 +317,38 @@ inline bool two_step_on(const fdtd_ctx* c) {
 // parity par ^ 1.
 // trial: a timing run that leaves the state alone (it writes only parity
 // par ^ 1; no plane sums, and the step count does not move).
-inline void ensure_side_streams(fdtd_ctx* c) {
-    if (c->side_ok) return;
-    SideStreams& q = c->side;
+inline void create_side_streams(SideStreams& q) {
+    q = SideStreams{};
     for (int i = 0; i < 3; ++i) {
         check(hipStreamCreateWithFlags(&q.s[i], hipStreamNonBlocking), "side stream");
         check(hipEventCreateWithFlags(&q.join[i], hipEventDisableTiming), "side event");
     }
     check(hipEventCreateWithFlags(&q.fork, hipEventDisableTiming), "side event");
+}
+
+inline void release_side_streams(SideStreams& q) {
+    for (int i = 0; i < 3; ++i) {
+        if (q.s[i]) (void)hipStreamDestroy(q.s[i]);
+        if (q.join[i]) (void)hipEventDestroy(q.join[i]);
+    }
+    if (q.fork) (void)hipEventDestroy(q.fork);
+    q = SideStreams{};
+}
+
+inline void ensure_side_streams(fdtd_ctx* c) {
+    if (c->side_ok) return;
+    try {
+        create_side_streams(c->side);
+    } catch (...) {
+        release_side_streams(c->side);
+        throw;
+    }
     c->side_ok = true;
 }
 
 inline void destroy_side_streams(fdtd_ctx* c) {
     if (!c->side_ok) return;
-    for (int i = 0; i < 3; ++i) {
-        if (c->side.s[i]) (void)hipStreamDestroy(c->side.s[i]);
-        if (c->side.join[i]) (void)hipEventDestroy(c->side.join[i]);
-    }
-    if (c->side.fork) (void)hipEventDestroy(c->side.fork);
-    c->side = SideStreams{};
+    release_side_streams(c->side);
     c->side_ok = false;
 }
 

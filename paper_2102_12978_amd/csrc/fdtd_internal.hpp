@@ -152,13 +152,15 @@ long long step2_interior_cells(const Problem& p, int rows);
 // The two-step kernel over many instances: work items (instance, segment,
 // row group, kb | ke << 16) per tile class (0 interior, 1 x boundary, 2 y
 // boundary, 3 corner; nz < 65536), and one pair of steps of every instance
-// (four launches on s, step index *nctr + off, parity par; diag: plane
-// accumulation as each Problem selects from its window on).
+// (four launches, step index *nctr + off, parity par; diag: plane
+// accumulation as each Problem selects from its window on). With side
+// streams the boundary classes run beside the interior one, forked from and
+// joined back into s (also under stream capture); without, all on s.
 void step2_batch_items(const std::vector<Problem>& probs, int rows, int zchunk,
                        std::vector<int4> items[4]);
 hipError_t launch_step2_batch(const Problem* probs, const int4* const items[4],
                               const int nitems[4], int rows, const long long* nctr, int off,
-                              int par, int diag, hipStream_t s);
+                              int par, int diag, hipStream_t s, const SideStreams* side);
 
 hipError_t launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 

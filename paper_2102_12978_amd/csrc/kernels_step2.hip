@@ -668,11 +668,17 @@ hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, in
         sy = side->s[1];
         sc = side->s[2];
     }
-    e = launch_class<TY, true, true>(p, n, parity, Launch2{s_bnd, g_bnd, P.cz, P.ncz}, mask0,
+    // The corner and y-boundary classes hold few tiles: shorter z chunks
+    // give them more workgroups (and a shorter critical path) at the cost
+    // of re-reading two planes at each chunk end.
+    const int czc = std::min(P.cz, 8), czy = std::min(P.cz, 16);
+    e = launch_class<TY, true, true>(p, n, parity,
+                                     Launch2{s_bnd, g_bnd, czc, (p.nz + czc - 1) / czc}, mask0,
                                      mask1, sc, timer, "step2_corner");
     if (e == hipSuccess)
-        e = launch_class<TY, false, true>(p, n, parity, Launch2{s_int, g_bnd, P.cz, P.ncz}, mask0,
-                                          mask1, sy, timer, "step2_ybnd");
+        e = launch_class<TY, false, true>(p, n, parity,
+                                          Launch2{s_int, g_bnd, czy, (p.nz + czy - 1) / czy},
+                                          mask0, mask1, sy, timer, "step2_ybnd");
     if (e == hipSuccess)
         e = launch_class<TY, true, false>(p, n, parity, Launch2{s_bnd, g_int, P.cz, P.ncz}, mask0,
                                           mask1, sx, timer, "step2_xbnd");
@@ -702,18 +708,34 @@ hipError_t launch_batch_class(const Problem* probs, const int4* items, int nitem
 template <int TY>
 hipError_t launch_batch_rows(const Problem* probs, const int4* const items[4],
                              const int nitems[4], const long long* nctr, int off, int par,
-                             int diag, hipStream_t s) {
-    hipError_t e = launch_batch_class<TY, true, true>(probs, items[3], nitems[3], nctr, off, par,
-                                                      diag, s);
+                             int diag, hipStream_t s, const SideStreams* side) {
+    hipStream_t sx = s, sy = s, sc = s;
+    hipError_t e = hipSuccess;
+    if (side) {
+        e = hipEventRecord(side->fork, s);
+        for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipStreamWaitEvent(side->s[q], side->fork, 0);
+        if (e != hipSuccess) return e;
+        sx = side->s[0];
+        sy = side->s[1];
+        sc = side->s[2];
+    }
+    e = launch_batch_class<TY, true, true>(probs, items[3], nitems[3], nctr, off, par, diag, sc);
     if (e == hipSuccess)
         e = launch_batch_class<TY, false, true>(probs, items[2], nitems[2], nctr, off, par, diag,
-                                                s);
+                                                sy);
     if (e == hipSuccess)
         e = launch_batch_class<TY, true, false>(probs, items[1], nitems[1], nctr, off, par, diag,
-                                                s);
+                                                sx);
     if (e == hipSuccess)
         e = launch_batch_class<TY, false, false>(probs, items[0], nitems[0], nctr, off, par,
                                                  diag, s);
+    if (side) {
+        for (int q = 0; q < 3; ++q) {
+            hipError_t f = hipEventRecord(side->join[q], side->s[q]);
+            if (f == hipSuccess) f = hipStreamWaitEvent(s, side->join[q], 0);
+            if (e == hipSuccess) e = f;
+        }
+    }
     return e;
 }
 
@@ -758,9 +780,11 @@ void step2_batch_items(const std::vector<Problem>& probs, int rows, int zchunk,
 
 hipError_t launch_step2_batch(const Problem* probs, const int4* const items[4],
                               const int nitems[4], int rows, const long long* nctr, int off,
-                              int par, int diag, hipStream_t s) {
-    if (rows == 2) return launch_batch_rows<2>(probs, items, nitems, nctr, off, par, diag, s);
-    if (rows == 4) return launch_batch_rows<4>(probs, items, nitems, nctr, off, par, diag, s);
+                              int par, int diag, hipStream_t s, const SideStreams* side) {
+    if (rows == 2)
+        return launch_batch_rows<2>(probs, items, nitems, nctr, off, par, diag, s, side);
+    if (rows == 4)
+        return launch_batch_rows<4>(probs, items, nitems, nctr, off, par, diag, s, side);
     return hipErrorInvalidValue;
 }
 
