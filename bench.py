@@ -23,7 +23,7 @@ BYTES_PER_CELL = 48            # read + write six FP32 field components
 CSRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc")
 # interior kernels: source file, committed PMC summary, cell-updates per cell and launch
 KERNELS = {
-    "step2_interior": ("kernels_step2.hip", "step2_interior_768x768x255_traffic.json", 2),
+    "step2_pass": ("kernels_step2.hip", "step2_pass_768x768x255_traffic.json", 2),
     "fused_interior": ("kernels_fused.hip", "fused_interior_768x768x255_traffic.json", 1),
 }
 
@@ -123,7 +123,7 @@ def cpu_baseline(full=False):
             "legs": out}
 
 
-def batch_measure(torch, stream, steps=1000, warmup=20):
+def batch_measure(torch, stream, steps=1000, warmup=20, graph_steps=20):
     """The 64-instance seed-1 sweep: autotuned work shape, 20-step graphs,
     mid-plane ⟨E_y²⟩ over the last 5 periods of each instance, then the
     per-instance deviation from the analytic beam (report only)."""
@@ -134,7 +134,7 @@ def batch_measure(torch, stream, steps=1000, warmup=20):
     ws = W.batch64_instances()
     b = Batch(ws, stream=stream.cuda_stream)
     cols, zc = b.autotune(3)
-    b.set_graph_steps(20)
+    b.set_graph_steps(graph_steps)
     total = warmup + steps
     for q, w in enumerate(ws):
         b[q].set_diagnostics(b[q].nz // 2, total - w.window_steps, L.DIAG_EY2)
@@ -210,7 +210,7 @@ def sequential_measure(torch, stream, ws, steps=200, warmup=20):
             "steps_each": steps, "ms_per_step_all": round(total_ms / steps, 4)}
 
 
-def adjoint_measure(torch, stream):
+def adjoint_measure(torch, stream, reps=3):
     """Gradient cost on the differentiable workload (192×192×61, 1500 steps,
     checkpoints every 100, 256 sector weights): forward with checkpoints +
     reverse sweep, against a plain 1500-step forward of the same problem."""
@@ -247,8 +247,8 @@ def adjoint_measure(torch, stream):
 
     plain()
     grad()
-    t_plain = min(plain()[0] for _ in range(3))
-    t_grad = min(grad()[0] for _ in range(3))
+    t_plain = min(plain()[0] for _ in range(reps))
+    t_grad = min(grad()[0] for _ in range(reps))
     inf = sens.adj.info()
     tb = s.info().time_block
     cells = s.nx * s.ny * s.nz
@@ -286,6 +286,12 @@ def main():
     ap.add_argument("--tb-zchunk", type=int, default=32, help="two-step kernel z chunk")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
+    ap.add_argument("--adjoint-reps", type=int, default=3,
+                    help="timed repetitions of each gradient-cost leg (minimum taken)")
+    ap.add_argument("--batch-graph-steps", type=int, default=20,
+                    help="steps per captured graph in the batch leg (0: eager launches)")
+    ap.add_argument("--no-step", action="store_true",
+                    help="skip the single-domain leg (profiling runs of the other legs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -301,123 +307,148 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    w = W.grid768()
-    s = Solver.from_workload(w, kernel=L.KERNEL_FUSED, stream=stream.cuda_stream)
-    s.set_workload_injector(w)
-    cells = s.nx * s.ny * s.nz
-    log(f"[bench] {w.name}: {s.nx}x{s.ny}x{s.nz} = {cells / 1e6:.1f} M cells")
-    if args.rows:
-        s.set_tile(args.rows, args.zchunk)
-    elif not args.no_tune:
-        rows, zc = s.autotune(3)
-        it = s.info()
-        log(f"[bench] autotuned: one-step tile rows={rows} zchunk={zc}; steps per pass "
-            f"{it.time_block} (two-step tile rows={it.tb_rows} zchunk={it.tb_zchunk})")
-    if args.time_block:
-        s.set_time_block(args.time_block, args.tb_rows, args.tb_zchunk)
-    s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    info = s.info()
-
-    # the headline: args.reps timed runs of exactly args.steps steps each,
-    # no per-launch events; value from the median run
-    runs = []
-    for _ in range(args.reps):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
+    if args.no_step:
+        out = {"metric": "Gcell-updates/s (Yee E+H+CPML+inject)", "value": None,
+               "note": "single-domain leg skipped (--no-step, a profiling run)"}
+    else:
+        w = W.grid768()
+        s = Solver.from_workload(w, kernel=L.KERNEL_FUSED, stream=stream.cuda_stream)
+        s.set_workload_injector(w)
+        cells = s.nx * s.ny * s.nz
+        log(f"[bench] {w.name}: {s.nx}x{s.ny}x{s.nz} = {cells / 1e6:.1f} M cells")
+        if args.rows:
+            s.set_tile(args.rows, args.zchunk)
+        elif not args.no_tune:
+            rows, zc = s.autotune(3)
+            it = s.info()
+            log(f"[bench] autotuned: one-step tile rows={rows} zchunk={zc}; steps per pass "
+                f"{it.time_block} (two-step tile rows={it.tb_rows} zchunk={it.tb_zchunk})")
+        if args.time_block:
+            s.set_time_block(args.time_block, args.tb_rows, args.tb_zchunk)
+        s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
+        s.step(args.warmup)
         torch.cuda.synchronize()
-        ev0.record(stream)
+        info = s.info()
+
+        # the headline: args.reps timed runs of exactly args.steps steps each,
+        # no per-launch events; value from the median run
+        runs = []
+        for _ in range(args.reps):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            s.step(args.steps)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            runs.append(ev0.elapsed_time(ev1))
+        total_ms = sorted(runs)[len(runs) // 2]
+        ms_per_step = total_ms / args.steps
+        value = cells * args.steps / (total_ms * 1e-3) / 1e9
+        log(f"[bench] {args.reps} x {args.steps} steps: " +
+            ", ".join(f"{r:.1f}" for r in runs) + f" ms -> median {value:.1f} Gcell/s")
+
+        # per-kernel launch times: one more run of args.steps steps with a HIP
+        # event pair around every launch, on the solver's stream
+        s.profile(True)
+        torch.cuda.synchronize()
         s.step(args.steps)
-        ev1.record(stream)
         torch.cuda.synchronize()
-        runs.append(ev0.elapsed_time(ev1))
-    total_ms = sorted(runs)[len(runs) // 2]
-    ms_per_step = total_ms / args.steps
-    value = cells * args.steps / (total_ms * 1e-3) / 1e9
-    log(f"[bench] {args.reps} x {args.steps} steps: " +
-        ", ".join(f"{r:.1f}" for r in runs) + f" ms -> median {value:.1f} Gcell/s")
+        prof = s.profile_read()
+        s.profile(False)
+        log(f"[bench] kernels: {prof}")
 
-    # per-kernel launch times: one more run of args.steps steps with a HIP
-    # event pair around every launch, on the solver's stream
-    s.profile(True)
-    torch.cuda.synchronize()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    prof = s.profile_read()
-    s.profile(False)
-    log(f"[bench] kernels: {prof}")
-
-    # the dominant kernel: the interior kernel that ran (the two-step one
-    # when pairs of steps go through it)
-    kname = next((k for k in KERNELS if k in prof), None)
-    roof = None
-    if kname:
-        kin = prof[kname]
-        avg_ms = kin[1] / kin[0]
-        upd = KERNELS[kname][2]
-        ncell = info.interior_cells
-        # algorithmic bytes: 48 B per cell-update (one read and one write of
-        # the six components), times the cell-updates of one launch
-        bytes_launch = BYTES_PER_CELL * upd * ncell
-        achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(kname), "kernel": kname,
-                "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": ncell,
-                "cell_updates_per_launch": upd * ncell,
-                "algorithmic_bytes_per_launch": bytes_launch,
-                # bytes the launch must move at least: each field read and
-                # written once per launch, whatever the steps it advances
-                "min_bytes_per_launch": BYTES_PER_CELL * ncell}
-    step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
-    if roof:
-        # what a kernel with no arithmetic reaches on the same GPU (context for frac)
-        from paper_2102_12978_amd.hbm_copy import stream_ceiling
-        ceil = stream_ceiling(stream=stream.cuda_stream)
-        roof["stream_ceiling"] = ceil
-        # the whole two-step pass: the four launches of each pair together
-        parts = [k for k in prof if k.startswith("step2_")]
-        if parts:
-            pair_ms = sum(prof[k][1] / prof[k][0] for k in parts)
-            roof["two_step_pass"] = {
-                "launches": {k: round(prof[k][1] / prof[k][0], 5) for k in parts},
-                "ms": round(pair_ms, 5), "cells": cells,
-                "achieved_gbs": round(BYTES_PER_CELL * 2 * cells / (pair_ms * 1e-3) / 1e9, 1)}
-        roof["frac_of_copy"] = round(roof["achieved"] / ceil["copy_gbs"], 4)
-        log(f"[bench] streaming probe: {ceil}")
-    out = {
-        "metric": "Gcell-updates/s (Yee E+H+CPML+inject)",
-        "value": round(value, 2),
-        "unit": "Gcell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "repetitions": args.reps,
-        "ms_per_run": [round(r, 3) for r in runs],
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "768x768x256 (z fitted to 255) Yee grid, dx=lambda/24, "
-                               "theta=20deg, order-2 Bessel antenna R=320dx, 16-cell CPML",
-                   "cells": cells, "steps_per_pass": info.time_block,
-                   "tile_rows": info.tb_rows if info.time_block == 2 else info.tile_rows,
-                   "tile_zchunk": info.tb_zchunk if info.time_block == 2 else info.tile_zchunk},
-        "step_hbm_fraction": round(step_gbs / HBM_PEAK_GBS, 4),
-        "kernels_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()},
-        "roofline": roof,
-    }
-    s.close()
+        roof = None
+        if info.time_block == 2 and "step2_interior" in prof:
+            # Two-step passes: the four tile-class launches of a pass run
+            # concurrently (the boundary classes on side streams) and the
+            # interior launch spans the pass, so the unit is the pass: 48 B per
+            # cell-update, two updates of every cell, over the pass time of
+            # the timed runs (events on the solver's stream, which forks and
+            # joins the side streams). The per-kernel figures come from one
+            # more run of the same passes with an event pair around each
+            # launch on its own stream.
+            pass_ms = total_ms / (args.steps / 2)
+            upd = 2 * cells
+            bytes_launch = BYTES_PER_CELL * upd
+            achieved = bytes_launch / (pass_ms * 1e-3) / 1e9
+            ki = prof["step2_interior"]
+            int_ms = ki[1] / ki[0]
+            int_bytes = BYTES_PER_CELL * 2 * info.interior_cells
+            int_gbs = int_bytes / (int_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("step2_pass"), "kernel": "step2_pass",
+                    "launch": "one two-step pass: interior, x-boundary, y-boundary and corner "
+                              "tile launches, concurrent",
+                    "avg_launch_ms": round(pass_ms, 5), "cells_per_launch": cells,
+                    "cell_updates_per_launch": upd,
+                    "algorithmic_bytes_per_launch": bytes_launch,
+                    # bytes a pass must move at least: each field read and
+                    # written once, whatever the steps it advances
+                    "min_bytes_per_launch": BYTES_PER_CELL * cells,
+                    "launches_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()
+                                    if k.startswith("step2_")},
+                    "interior_launch": {
+                        "avg_ms": round(int_ms, 5), "cells": info.interior_cells,
+                        "cell_updates": 2 * info.interior_cells,
+                        "achieved": round(int_gbs, 1),
+                        "frac": round(int_gbs / HBM_PEAK_GBS, 4)}}
+        else:
+            # one step per launch: the dominant kernel is the interior kernel
+            kname = next((k for k in KERNELS if k in prof and KERNELS[k][2] == 1), None)
+            if kname:
+                kin = prof[kname]
+                avg_ms = kin[1] / kin[0]
+                ncell = info.interior_cells
+                bytes_launch = BYTES_PER_CELL * ncell
+                achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+                roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(kname), "kernel": kname,
+                        "avg_launch_ms": round(avg_ms, 5), "cells_per_launch": ncell,
+                        "cell_updates_per_launch": ncell,
+                        "algorithmic_bytes_per_launch": bytes_launch}
+        step_gbs = BYTES_PER_CELL * cells / (ms_per_step * 1e-3) / 1e9
+        if roof:
+            # what a kernel with no arithmetic reaches on the same GPU (context for frac)
+            from paper_2102_12978_amd.hbm_copy import stream_ceiling
+            ceil = stream_ceiling(stream=stream.cuda_stream)
+            roof["stream_ceiling"] = ceil
+            roof["frac_of_copy"] = round(roof["achieved"] / ceil["copy_gbs"], 4)
+            log(f"[bench] streaming probe: {ceil}")
+        out = {
+            "metric": "Gcell-updates/s (Yee E+H+CPML+inject)",
+            "value": round(value, 2),
+            "unit": "Gcell-updates/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "repetitions": args.reps,
+            "ms_per_run": [round(r, 3) for r in runs],
+            "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "768x768x256 (z fitted to 255) Yee grid, dx=lambda/24, "
+                                   "theta=20deg, order-2 Bessel antenna R=320dx, 16-cell CPML",
+                       "cells": cells, "steps_per_pass": info.time_block,
+                       "tile_rows": info.tb_rows if info.time_block == 2 else info.tile_rows,
+                       "tile_zchunk": info.tb_zchunk if info.time_block == 2 else info.tile_zchunk},
+            "step_hbm_fraction": round(step_gbs / HBM_PEAK_GBS, 4),
+            "kernels_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()},
+            "roofline": roof,
+        }
+        s.close()
     if not args.no_batch:
         log("[bench] 64-instance batch ...")
-        out["batch"] = batch_measure(torch, stream)
+        out["batch"] = batch_measure(torch, stream, graph_steps=args.batch_graph_steps)
         log(f"[bench] batch: {out['batch']['value']} Gcell/s")
     if not args.no_adjoint:
         log("[bench] adjoint gradient cost ...")
-        out["adjoint"] = adjoint_measure(torch, stream)
+        out["adjoint"] = adjoint_measure(torch, stream, max(1, args.adjoint_reps))
         log(f"[bench] adjoint: {out['adjoint']}")
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")

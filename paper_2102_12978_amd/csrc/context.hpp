@@ -22,19 +22,33 @@ struct EventTimer : bfdtd::LaunchTimer {
     };
     std::vector<Rec> open_;
     std::vector<std::pair<std::string, std::pair<long long, double>>> totals;
-    int pending = -1;
-    void mark(const char* name) override {
+    // the record each stream has open (the event recorded next on that
+    // stream closes it)
+    std::vector<std::pair<hipStream_t, int>> pending;
+    void mark(const char* name) override { mark_on(name, stream); }
+    void mark_on(const char* name, hipStream_t s) override {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
-        (void)hipEventRecord(e, stream);
-        if (pending >= 0) open_[pending].b = e;
-        pending = -1;
+        (void)hipEventRecord(e, s);
+        bool used = false;
+        int* slot = nullptr;
+        for (auto& q : pending)
+            if (q.first == s) slot = &q.second;
+        if (!slot) {
+            pending.push_back({s, -1});
+            slot = &pending.back().second;
+        }
+        if (*slot >= 0) {
+            open_[*slot].b = e;
+            used = true;
+        }
+        *slot = -1;
         if (name) {
             open_.push_back(Rec{name, e, nullptr});
-            pending = (int)open_.size() - 1;
-        } else if (open_.empty() || open_.back().b != e) {
-            (void)hipEventDestroy(e);
+            *slot = (int)open_.size() - 1;
+            used = true;
         }
+        if (!used) (void)hipEventDestroy(e);
     }
     void collect() {
         std::vector<hipEvent_t> seen;
@@ -62,7 +76,7 @@ struct EventTimer : bfdtd::LaunchTimer {
             }
         }
         open_.clear();
-        pending = -1;
+        pending.clear();
     }
     ~EventTimer() override { collect(); }
 };

@@ -105,9 +105,12 @@ void cpml_axis_tables(int n, int npml, double delta_ratio, const fdtd_grid& g, d
 std::string validate_grid(const fdtd_grid& g);
 
 // Optional per-launch timing: launchers call mark(name) before each kernel
-// and mark(nullptr) after the last one.
+// and mark(nullptr) after the last one, on the timer's own stream; a
+// launcher that spreads kernels over several streams brackets each one with
+// mark_on(name, s) and mark_on(nullptr, s) on that kernel's stream.
 struct LaunchTimer {
     virtual void mark(const char* name) = 0;
+    virtual void mark_on(const char* name, hipStream_t s) = 0;
     virtual ~LaunchTimer() {}
 };
 

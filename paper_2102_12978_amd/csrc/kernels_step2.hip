@@ -640,24 +640,24 @@ hipError_t launch_class(const Problem& p, long long n, int parity, const Launch2
     const int nt = span_count(L.seg) * span_count(L.grp) * L.ncz;
     if (nt <= 0) return hipSuccess;
     const int nbp = (nt + 7) / 8 * 8;
-    if (timer) timer->mark(name);
+    if (timer) timer->mark_on(name, s);
     hipLaunchKernelGGL((step2_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES), 0, s, p, n,
                        parity, L, nbp, mask0, mask1);
     hipError_t e = hipGetLastError();
-    if (timer) timer->mark(nullptr);
+    if (timer) timer->mark_on(nullptr, s);
     return e;
 }
 
-// The four classes touch disjoint cells: with side streams (and no
-// per-launch timer) the boundary classes run beside the interior launch,
-// forked from and joined back into s by events.
+// The four classes touch disjoint cells: with side streams the boundary
+// classes run beside the interior launch, forked from and joined back into
+// s by events (a per-launch timer brackets each kernel on its own stream).
 template <int TY>
 hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, int mask0,
                        int mask1, hipStream_t s, LaunchTimer* timer, const SideStreams* side) {
     const Plan2 P = plan2(p, TY, zchunk);
     const Span s_int{P.s_lo, P.s_hi, 0, 0}, s_bnd{0, P.s_lo, P.s_hi, P.nseg};
     const Span g_int{P.g_lo, P.g_hi, 0, 0}, g_bnd{0, P.g_lo, P.g_hi, P.ngrp};
-    const bool fork = side && !timer;
+    const bool fork = side != nullptr;
     hipStream_t sx = s, sy = s, sc = s;
     hipError_t e;
     if (fork) {
