@@ -288,6 +288,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     ap.add_argument("--adjoint-reps", type=int, default=3,
                     help="timed repetitions of each gradient-cost leg (minimum taken)")
+    ap.add_argument("--sequential-classes", action="store_true",
+                    help="run the two-step boundary launches after the interior one instead "
+                         "of beside it (times each launch alone; a measurement run)")
     ap.add_argument("--batch-graph-steps", type=int, default=20,
                     help="steps per captured graph in the batch leg (0: eager launches)")
     ap.add_argument("--no-step", action="store_true",
@@ -325,6 +328,8 @@ def main():
                 f"{it.time_block} (two-step tile rows={it.tb_rows} zchunk={it.tb_zchunk})")
         if args.time_block:
             s.set_time_block(args.time_block, args.tb_rows, args.tb_zchunk)
+        if args.sequential_classes:
+            s.set_concurrency(False)
         s.set_diagnostics(s.nz // 2, 0, L.DIAG_EY2)
         s.step(args.warmup)
         torch.cuda.synchronize()
@@ -380,7 +385,8 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic("step2_pass"), "kernel": "step2_pass",
                     "launch": "one two-step pass: interior, x-boundary, y-boundary and corner "
-                              "tile launches, concurrent",
+                              "tile launches, " + ("one after another" if args.sequential_classes
+                                                   else "concurrent"),
                     "avg_launch_ms": round(pass_ms, 5), "cells_per_launch": cells,
                     "cell_updates_per_launch": upd,
                     "algorithmic_bytes_per_launch": bytes_launch,
@@ -435,6 +441,7 @@ def main():
             "config": {"workload": "768x768x256 (z fitted to 255) Yee grid, dx=lambda/24, "
                                    "theta=20deg, order-2 Bessel antenna R=320dx, 16-cell CPML",
                        "cells": cells, "steps_per_pass": info.time_block,
+                       "classes_concurrent": not args.sequential_classes,
                        "tile_rows": info.tb_rows if info.time_block == 2 else info.tile_rows,
                        "tile_zchunk": info.tb_zchunk if info.time_block == 2 else info.tile_zchunk},
             "step_hbm_fraction": round(step_gbs / HBM_PEAK_GBS, 4),

@@ -346,6 +346,13 @@ int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
  * last step runs alone. */
 int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchunk);
 
+/* Whether the two-step kernel's three boundary launches run beside the
+ * interior one on the context's side streams (on = 1, the default) or one
+ * after another on the context's stream (on = 0), for example to time each
+ * launch alone with fdtd_profile_enable. Results are the same bit for bit
+ * either way. FDTD_EINVAL for other values. */
+int fdtd_set_concurrency(fdtd_ctx *ctx, int32_t on);
+
 /* Time candidate tile shapes and frame choices on the live problem (the state
  * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
  * frames, and, except in the periodic test mode, the two-step kernel

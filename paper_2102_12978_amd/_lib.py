@@ -118,6 +118,7 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_int32)]),
     "fdtd_set_frame": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "fdtd_set_time_block": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "fdtd_set_concurrency": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_enable": (ctypes.c_int, [_CTX, ctypes.c_int32]),
     "fdtd_profile_read": (ctypes.c_int, [_CTX, ctypes.POINTER(KernelProfile), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),

@@ -596,6 +596,14 @@ int fdtd_set_time_block(fdtd_ctx* c, int32_t steps, int32_t rows, int32_t zchunk
     });
 }
 
+int fdtd_set_concurrency(fdtd_ctx* c, int32_t on) {
+    if (!c) return FDTD_EINVAL;
+    return guarded(c, [&] {
+        need(on == 0 || on == 1, "on must be 0 or 1");
+        c->concurrent = on != 0;
+    });
+}
+
 int fdtd_set_frame(fdtd_ctx* c, int32_t kind, int32_t xalign, int32_t rows) {
     if (!c) return FDTD_EINVAL;
     if (c->batch_owned) {

@@ -124,6 +124,7 @@ struct fdtd_ctx {
     int time_block = 1, tb_rows = 4, tb_zchunk = 0;
     bfdtd::SideStreams side{};     // the two-step kernel's boundary launches
     bool side_ok = false;
+    bool concurrent = true;        // boundary launches beside the interior (else in order)
     bool batch_owned = false;      // stepped by an fdtd_batch
     // bumped by every change of the antenna or its sector weights: an
     // adjoint's reverse sweep refuses to run on checkpoints of another antenna
@@ -373,9 +374,9 @@ inline void launch_pair(fdtd_ctx* c, long long n, bool trial = false) {
     const unsigned dm = trial ? 0u : c->mask & 7u;
     const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
     const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
-    ensure_side_streams(c);
+    if (c->concurrent) ensure_side_streams(c);
     check(launch_step2(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, c->stream, c->timer,
-                       &c->side),
+                       c->concurrent ? &c->side : nullptr),
           "two-step launch");
     if (trial) return;
     c->count += (m0 != 0) + (m1 != 0);

@@ -278,6 +278,11 @@ class Solver:
         with tiles of `rows` rows and z chunks of `zchunk` planes)."""
         self._c(self._lib.fdtd_set_time_block(self._ctx, int(steps), int(rows), int(zchunk)))
 
+    def set_concurrency(self, on=True):
+        """fdtd_set_concurrency: boundary launches beside the interior (True)
+        or one after another (False)."""
+        self._c(self._lib.fdtd_set_concurrency(self._ctx, 1 if on else 0))
+
     def profile(self, on=True):
         self._c(self._lib.fdtd_profile_enable(self._ctx, 1 if on else 0))
 

@@ -283,3 +283,23 @@ def test_rows_two_and_antenna_across_boundary_tiles():
     GC.assert_parity(two.fields(), [st.f[c] for c in GC.COMPS], "two-step rows 2")
     one.close()
     two.close()
+
+
+def test_boundary_launches_in_order_equal_concurrent():
+    """fdtd_set_concurrency(0) runs the three boundary launches after the
+    interior one on the context's stream: the same state bit for bit as the
+    default concurrent launches; values other than 0 and 1 are refused."""
+    w = W.parity_mid()
+    a, b = (GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=0) for _ in range(2))
+    for s in (a, b):
+        s.set_time_block(2, 2, 8)
+    b.set_concurrency(False)
+    with pytest.raises(L.FdtdError) as e:
+        b._c(b._lib.fdtd_set_concurrency(b._ctx, 2))
+    assert e.value.code == L.EINVAL
+    _random_start((a, b), w, seed=5)
+    for s in (a, b):
+        s.step(12)
+    _assert_identical(a, b, w, "in order vs concurrent")
+    for s in (a, b):
+        s.close()

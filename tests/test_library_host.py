@@ -146,6 +146,7 @@ def test_polarisation_constants_match_the_header():
 def test_time_block_setter_rejects_null_handle():
     lib = L.load()
     assert lib.fdtd_set_time_block(None, 2, 4, 0) == L.EINVAL
+    assert lib.fdtd_set_concurrency(None, 1) == L.EINVAL
 
 
 # ctypes structure -> C type name in include/fdtd.h
