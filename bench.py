@@ -107,8 +107,13 @@ def cpu_baseline(full=False):
     except AttributeError:
         avail = os.cpu_count()
     workers = max(1, min(len(legs), avail))
+    from concurrent.futures import as_completed
+    res = {}
     with ProcessPoolExecutor(max_workers=workers) as ex:
-        res = dict(zip(legs, ex.map(_oracle_leg, legs.values())))
+        futs = {ex.submit(_oracle_leg, v): k for k, v in legs.items()}
+        for f in as_completed(futs):
+            res[futs[f]] = f.result()
+            log(f"[bench] CPU leg {futs[f]}: {res[futs[f]][1]:.1f} s")
     out = {}
     for k, (name, steps, inst) in legs.items():
         upd, secs = res[k]
