@@ -215,6 +215,59 @@ def sequential_measure(torch, stream, ws, steps=200, warmup=20):
             "steps_each": steps, "ms_per_step_all": round(total_ms / steps, 4)}
 
 
+def shard_measure(torch, stream, parts, steps=1000, warmup=20, reps=5):
+    """One GPU's share of the 768×768×255 grid cut into `parts` z-slabs on a
+    ring: 768×768×round(255/parts) planes, z periodic over the slab (the wrap
+    stands in for the neighbour exchange, so no exchange is timed), same
+    Δx, Δz, CPML, antenna and diagnostics as the whole grid (the antenna's
+    axial phase does not close over the slab; the work per step does not
+    depend on it). Autotuned like the headline leg; median of `reps` runs."""
+    from paper_2102_12978_amd import _lib as L
+    from paper_2102_12978_amd import workloads as W
+    from paper_2102_12978_amd.solver import Solver
+    w = W.grid768()
+    (nx, ny, nz_full, dx, dy, dz), kw = Solver.workload_grid_args(w)
+    nz = int(round(nz_full / parts))
+    s = Solver(nx, ny, nz, dx, dy, dz, kernel=L.KERNEL_FUSED, stream=stream.cuda_stream, **kw)
+    s.set_workload_injector(w, allow_z_misfit=True)
+    s.autotune(3)
+    s.set_diagnostics(nz // 2, 0, L.DIAG_EY2)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        s.step(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(ev0.elapsed_time(ev1))
+    ms = sorted(runs)[len(runs) // 2] / steps
+    it = s.info()
+    cells = nx * ny * nz
+    s.close()
+    # what a two-step pass would need from its ring neighbours (derived from
+    # the planes a z chunk reads beyond its ends, not measured): below, all
+    # six components of the plane under the slab and H_x, H_y of the one
+    # under that; above, all six of the plane over the slab and all but E_z
+    # of the one over that
+    plane_bytes = nx * ny * 4
+    return {
+        "workload": f"768x768x{nz}: one of {parts} z-slabs of the 768x768x255 grid, z periodic "
+                    "over the slab in place of the neighbour exchange",
+        "cells": cells, "steps": steps, "repetitions": reps,
+        "ms_per_step": round(ms, 5),
+        "value": round(cells / (ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
+        "steps_per_pass": it.time_block,
+        "tile_rows": it.tb_rows if it.time_block == 2 else it.tile_rows,
+        "tile_zchunk": it.tb_zchunk if it.time_block == 2 else it.tile_zchunk,
+        "halo_bytes_per_pass_from_below": 8 * plane_bytes,
+        "halo_bytes_per_pass_from_above": 11 * plane_bytes,
+    }
+
+
 def adjoint_measure(torch, stream, reps=3):
     """Gradient cost on the differentiable workload (192×192×61, 1500 steps,
     checkpoints every 100, 256 sector weights): forward with checkpoints +
@@ -300,6 +353,9 @@ def main():
                     help="steps per captured graph in the batch leg (0: eager launches)")
     ap.add_argument("--no-step", action="store_true",
                     help="skip the single-domain leg (profiling runs of the other legs)")
+    ap.add_argument("--shard", type=int, default=8,
+                    help="also time one GPU's z-slab share of the grid cut into this many "
+                         "slabs (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -454,6 +510,10 @@ def main():
             "roofline": roof,
         }
         s.close()
+    if args.shard > 1 and not args.no_step:
+        log(f"[bench] z-slab share of {args.shard} ...")
+        out["shard"] = shard_measure(torch, stream, args.shard)
+        log(f"[bench] shard: {out['shard']}")
     if not args.no_batch:
         log("[bench] 64-instance batch ...")
         out["batch"] = batch_measure(torch, stream, graph_steps=args.batch_graph_steps)
