@@ -32,6 +32,20 @@ __device__ __forceinline__ float2 ld2(gptr<const float2> q, size_t i) {
     return make_float2(v.x, v.y);
 }
 
+// float2 element i of a table no kernel writes (the z phases e^{iβz}, the
+// time factors), read through the constant address space: with a
+// wavefront-uniform index that is a scalar load, whose wait leaves the
+// vector-memory counter, and so the wavefront's field loads and stores in
+// flight, alone. A lane-varying index still gives a vector load.
+template <typename T>
+using cptr = __attribute__((address_space(4))) const T*;
+
+__device__ __forceinline__ float2 ldc2(const float2* q, size_t i) {
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = ((cptr<v2f>)q)[i];
+    return make_float2(v.x, v.y);
+}
+
 // CPML slab index of an x position (-1 outside the slabs).
 __device__ __forceinline__ int slab_index(int i, int n, int npml) {
     if (npml <= 0) return -1;

@@ -108,9 +108,9 @@ __device__ __forceinline__ void e_plane(const Problem& p, int lane, long long n,
                                         float (&ex)[TY + 1], float (&ey)[TY], float (&ez)[TY + 1]) {
     float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
     if (p.colmap) {
-        const float2 t = p.tE[n];
-        pt0 = cmul(p.zph[2 * kk], t);
-        pt1 = cmul(p.zph[2 * kk + 1], t);
+        const float2 t = ldc2(p.tE, n);
+        pt0 = cmul(ldc2(p.zph, 2 * kk), t);
+        pt1 = cmul(ldc2(p.zph, 2 * kk + 1), t);
     }
 #pragma unroll
     for (int r = 0; r <= TY; ++r) {
@@ -184,9 +184,9 @@ __device__ __forceinline__ void e_halo_right(const Problem& p, long long n, int 
     using Hq = Halo<TY>;
     float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
     if (p.colmap) {
-        const float2 t = p.tE[n];
-        pt0 = cmul(p.zph[2 * kk], t);
-        pt1 = cmul(p.zph[2 * kk + 1], t);
+        const float2 t = ldc2(p.tE, n);
+        pt0 = cmul(ldc2(p.zph, 2 * kk), t);
+        pt1 = cmul(ldc2(p.zph, 2 * kk + 1), t);
     }
     float hx_prev = bcast(g, Hq::R_HX);
 #pragma unroll
@@ -314,7 +314,7 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
         hcy[TY] = hy[TY];
         store_e(kb, ecx, ecy, ecz);
     }
-    const float2 th = p.colmap ? p.tH[n] : make_float2(0.f, 0.f);
+    const float2 th = p.colmap ? ldc2(p.tH, n) : make_float2(0.f, 0.f);
 
     for (int k = kb; k < ke; ++k) {
         const int kn = k + 1 == nz ? 0 : k + 1;
@@ -341,8 +341,8 @@ fused_interior_kernel(Problem p, long long n, int par, Interior I, int nblocks_p
         // ---- H_new(k) ---------------------------------------------------
         float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
         if (p.colmap) {
-            qt0 = cmul(p.zph[2 * k], th);
-            qt1 = cmul(p.zph[2 * k + 1], th);
+            qt0 = cmul(ldc2(p.zph, 2 * k), th);
+            qt1 = cmul(ldc2(p.zph, 2 * k + 1), th);
         }
 #pragma unroll
         for (int r = 0; r < TY; ++r) {

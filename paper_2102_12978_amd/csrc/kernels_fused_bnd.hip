@@ -163,9 +163,9 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
                          float (&ey)[TY + 1], float (&ez)[TY + 1]) {
             float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
             if (p.colmap) {
-                const float2 tt = ld2(G(p.tE), n);
-                pt0 = cmul(ld2(G(p.zph), 2 * kk), tt);
-                pt1 = cmul(ld2(G(p.zph), 2 * kk + 1), tt);
+                const float2 tt = ldc2(p.tE, n);
+                pt0 = cmul(ldc2(p.zph, 2 * kk), tt);
+                pt1 = cmul(ldc2(p.zph, 2 * kk + 1), tt);
             }
 #pragma unroll
             for (int r = 0; r <= TY; ++r) {
@@ -198,9 +198,9 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
         auto e_right = [&](int kk, const float (&hy)[TY + 1], const float (&hz)[TY + 2], float g) {
             float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
             if (p.colmap) {
-                const float2 tt = ld2(G(p.tE), n);
-                pt0 = cmul(ld2(G(p.zph), 2 * kk), tt);
-                pt1 = cmul(ld2(G(p.zph), 2 * kk + 1), tt);
+                const float2 tt = ldc2(p.tE, n);
+                pt0 = cmul(ldc2(p.zph, 2 * kk), tt);
+                pt1 = cmul(ldc2(p.zph, 2 * kk + 1), tt);
             }
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
@@ -289,7 +289,7 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             }
             store_e(kb, ex, ey, ez);
         }
-        const float2 th = p.colmap ? ld2(G(p.tH), n) : make_float2(0.f, 0.f);
+        const float2 th = p.colmap ? ldc2(p.tH, n) : make_float2(0.f, 0.f);
 
         for (int k = kb; k < ke; ++k) {
             const int kn = k + 1 == nz ? 0 : k + 1;
@@ -318,8 +318,8 @@ fused_bnd_kernel(Problem single, const Problem* __restrict__ probs, const int4* 
             e_right(kn, hy, hz, gn);
             float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
             if (p.colmap) {
-                qt0 = cmul(ld2(G(p.zph), 2 * k), th);
-                qt1 = cmul(ld2(G(p.zph), 2 * k + 1), th);
+                qt0 = cmul(ldc2(p.zph, 2 * k), th);
+                qt1 = cmul(ldc2(p.zph, 2 * k + 1), th);
             }
 #pragma unroll
             for (int r = 0; r < TY; ++r) {

@@ -19,6 +19,13 @@
 //   z: at plane q the pipeline forms E^{n+1}(q), H^{n+3/2}(q-1),
 //      E^{n+2}(q-1) and H^{n+5/2}(q-2), keeping one plane of each in
 //      registers; a chunk [kb, ke) reads planes kb-2 .. ke+1 (z is periodic).
+// Waits. On this chip one counter tracks a wavefront's vector-memory loads
+// and stores together, so waiting for any vector load also waits for every
+// older load and store. A plane therefore issues all its vector loads at
+// its start (fields and CPML memories; interior tiles load the next plane's
+// H rows at the end of the previous one, beside its stores), reads the z
+// phases e^{iβz} with scalar loads and the antenna amplitudes from LDS, and
+// waits on vector memory only for the plane's own field loads.
 // A workgroup stacks four wavefronts in y that start every plane together
 // (one barrier per plane): a row group of 4 TY rows.
 //
@@ -210,17 +217,38 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
         slot[O + r] = inb ? v : -1;
     }
     const gptr<const float2> amp = G(p.amp);
-    const float2 tE0 = src ? ld2(G(p.tE), n) : make_float2(0.f, 0.f);
-    const float2 tE1 = src ? ld2(G(p.tE), n + 1) : make_float2(0.f, 0.f);
-    const float2 tH0 = src ? ld2(G(p.tH), n) : make_float2(0.f, 0.f);
-    const float2 tH1 = src ? ld2(G(p.tH), n + 1) : make_float2(0.f, 0.f);
-    // e^{iβz} at the integer / half planes of kk times a time factor
-    auto phase = [&](int kk, float2 tt, float2& a0, float2& a1) {
+    // The antenna amplitudes of the rows a wavefront forms (-1 .. TY+1), one
+    // float2 per (row, component, lane), staged in LDS once per tile: the
+    // stages read them with LDS loads, whose waits leave the vector-memory
+    // counter alone (a vector load's wait would also wait for the field
+    // loads and stores in flight). The workgroup's rows are laid out from
+    // row -1 of its first wavefront; rows two stacked wavefronts share are
+    // written by both with the same values, and a wavefront reads only rows
+    // it wrote itself.
+    extern __shared__ float2 amp_lds[];
+    auto lds_at = [&](int r, int c) { return ((w * TY + r + 1) * 6 + c) * 64 + lane; };
+    if (src) {
+#pragma unroll
+        for (int r = -1; r <= TY + 1; ++r) {
+            if (slot[O + r] >= 0) {
+                const gptr<const float2> a = amp + (size_t)slot[O + r] * 6;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) amp_lds[lds_at(r, c)] = ld2(a, c);
+            }
+        }
+    }
+    const float2 tE0 = src ? ldc2(p.tE, n) : make_float2(0.f, 0.f);
+    const float2 tE1 = src ? ldc2(p.tE, n + 1) : make_float2(0.f, 0.f);
+    const float2 tH0 = src ? ldc2(p.tH, n) : make_float2(0.f, 0.f);
+    const float2 tH1 = src ? ldc2(p.tH, n + 1) : make_float2(0.f, 0.f);
+    // e^{iβz} at the integer / half planes of a plane (z0, z1) times a time
+    // factor
+    auto phase = [&](float2 z0, float2 z1, float2 tt, float2& a0, float2& a1) {
         a0 = make_float2(0.f, 0.f);
         a1 = a0;
         if (src) {
-            a0 = cmul(ld2(G(p.zph), 2 * kk), tt);
-            a1 = cmul(ld2(G(p.zph), 2 * kk + 1), tt);
+            a0 = cmul(z0, tt);
+            a1 = cmul(z1, tt);
         }
     };
     const gptr<double> fl = G(p.fl);
@@ -325,6 +353,20 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
     while (kq < 0) kq += nz;
     kq %= nz;
     int kq1 = 0, kq2 = 0;   // planes of q-1, q-2
+    // e^{iβz} of planes q-1 and q-2 (integer, half plane), carried
+    float2 za0 = make_float2(0.f, 0.f), za1 = za0, zb0 = za0, zb1 = za0;
+    // interior tiles: the next plane's H rows are loaded at the end of a
+    // plane, beside its stores
+    constexpr bool PF = !XB && !YB;
+    float nhx[TY + 4], nhy[TY + 4], nhz[TY + 4];
+    if constexpr (PF) {
+#pragma unroll
+        for (int r = -2; r <= TY + 1; ++r) {
+            nhx[O + r] = ld(HX, kq, r);
+            nhz[O + r] = ld(HZ, kq, r);
+            if (r >= -1) nhy[O + r] = ld(HY, kq, r);
+        }
+    }
     for (int q = kb - 2; q <= ke + 1; ++q) {
         // The four wavefronts of the workgroup start each plane together, so
         // the halo rows one loads are the rows its neighbour loads in the
@@ -334,31 +376,49 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
         float hx[TY + 4], hy[TY + 4], hz[TY + 4], ex[TY + 4], ey[TY + 4], ez[TY + 4];
 #pragma unroll
         for (int r = -2; r <= TY + 1; ++r) {
-            hx[O + r] = ld(HX, kq, r);
-            hz[O + r] = ld(HZ, kq, r);
+            hx[O + r] = PF ? nhx[O + r] : ld(HX, kq, r);
+            hz[O + r] = PF ? nhz[O + r] : ld(HZ, kq, r);
             if (r >= -1) {
-                hy[O + r] = ld(HY, kq, r);
+                hy[O + r] = PF ? nhy[O + r] : ld(HY, kq, r);
                 ex[O + r] = ld(EX, kq, r);
                 ez[O + r] = ld(EZ, kq, r);
             }
             if (r >= -1 && r <= TY) ey[O + r] = ld(EY, kq, r);
         }
+        float2 zq0 = make_float2(0.f, 0.f), zq1 = zq0;   // e^{iβz} of plane q
+        if (src) {
+            zq0 = ldc2(p.zph, 2 * kq);
+            zq1 = ldc2(p.zph, 2 * kq + 1);
+        }
+        // CPML memories of both stages, issued with the field loads
+        float pe_yx[PX], pe_zx[PX], pe_xy[PY], pe_zy[PY];   // ψ_E^n(q)
+        float ph_yx[PX], ph_zx[PX], ph_xy[PY], ph_zy[PY];   // ψ_H^{n+1/2}(q-1)
+#pragma unroll
+        for (int r = -1; r <= TY + 1; ++r) {
+            if constexpr (XB) {
+                pe_yx[O + r] = r <= TY ? ldx(P_EYX, kq, r) : 0.f;
+                pe_zx[O + r] = ldx(P_EZX, kq, r);
+                if (r <= TY) {
+                    ph_yx[O + r] = r >= 0 ? ldx(P_HYX, kq1, r) : 0.f;
+                    ph_zx[O + r] = ldx(P_HZX, kq1, r);
+                }
+            }
+            if constexpr (YB) {
+                pe_xy[O + r] = ldy(P_EXY, kq, r);
+                pe_zy[O + r] = ldy(P_EZY, kq, r);
+                if (r <= TY) {
+                    ph_xy[O + r] = ldy(P_HXY, kq1, r);
+                    ph_zy[O + r] = ldy(P_HZY, kq1, r);
+                }
+            }
+        }
 
         // ---- E^{n+1}(q), rows -1 .. TY+1 (E_y to TY), in place ------------
-        float pe_yx[PX], pe_zx[PX], pe_xy[PY], pe_zy[PY];   // ψ_E of this stage
         {
             float2 pt0, pt1;
-            phase(kq, tE0, pt0, pt1);
+            phase(zq0, zq1, tE0, pt0, pt1);
 #pragma unroll
             for (int r = -1; r <= TY + 1; ++r) {
-                if constexpr (XB) {
-                    pe_yx[O + r] = r <= TY ? ldx(P_EYX, kq, r) : 0.f;
-                    pe_zx[O + r] = ldx(P_EZX, kq, r);
-                }
-                if constexpr (YB) {
-                    pe_xy[O + r] = ldy(P_EXY, kq, r);
-                    pe_zy[O + r] = ldy(P_EZY, kq, r);
-                }
                 if (r > TY) ey[O + r] = 0.f;   // E_y is not formed on the last row
                 const float hz_im = from_lower(hz[O + r]);
                 const float hy_im = from_lower(hy[O + r]);
@@ -368,10 +428,9 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
                       hx[O + r] - hx[O + r - 1], RX(pe_yx, r), RX(pe_zx, r), RY(pe_xy, r),
                       RY(pe_zy, r), r <= TY);
                 if (slot[O + r] >= 0) {
-                    const gptr<const float2> a = amp + (size_t)slot[O + r] * 6;
-                    ex[O + r] += cmul_re(ld2(a, EX), pt0);
-                    ez[O + r] += cmul_re(ld2(a, EZ), pt1);
-                    if (r <= TY) ey[O + r] += cmul_re(ld2(a, EY), pt0);
+                    ex[O + r] += cmul_re(amp_lds[lds_at(r, EX)], pt0);
+                    ez[O + r] += cmul_re(amp_lds[lds_at(r, EZ)], pt1);
+                    if (r <= TY) ey[O + r] += cmul_re(amp_lds[lds_at(r, EY)], pt0);
                 }
                 zero_out(r, ex[O + r], ey[O + r], ez[O + r]);
             }
@@ -384,20 +443,11 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
 
         // ---- H^{n+3/2}(q-1), rows -1 .. TY (H_y from 0) --------------------
         float gx[TY + 4], gy[TY + 4], gz[TY + 4];
-        float ph_yx[PX], ph_zx[PX], ph_xy[PY], ph_zy[PY];   // ψ_H of this stage
         {
             float2 qt0, qt1;
-            phase(kq1, tH0, qt0, qt1);
+            phase(za0, za1, tH0, qt0, qt1);
 #pragma unroll
             for (int r = -1; r <= TY; ++r) {
-                if constexpr (XB) {
-                    ph_yx[O + r] = r >= 0 ? ldx(P_HYX, kq1, r) : 0.f;
-                    ph_zx[O + r] = ldx(P_HZX, kq1, r);
-                }
-                if constexpr (YB) {
-                    ph_xy[O + r] = ldy(P_HXY, kq1, r);
-                    ph_zy[O + r] = ldy(P_HZY, kq1, r);
-                }
                 const float ey_ip = from_upper(e1y[O + r]);
                 const float ez_ip = from_upper(e1z[O + r]);
                 gx[O + r] = hpx[O + r];
@@ -408,10 +458,9 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
                       ey_ip - e1y[O + r], e1x[O + r + 1] - e1x[O + r], RX(ph_yx, r),
                       RX(ph_zx, r), RY(ph_xy, r), RY(ph_zy, r), r >= 0);
                 if (slot[O + r] >= 0) {
-                    const gptr<const float2> a = amp + (size_t)slot[O + r] * 6;
-                    gx[O + r] += cmul_re(ld2(a, HX), qt1);
-                    if (r >= 0) gy[O + r] += cmul_re(ld2(a, HY), qt1);
-                    gz[O + r] += cmul_re(ld2(a, HZ), qt0);
+                    gx[O + r] += cmul_re(amp_lds[lds_at(r, HX)], qt1);
+                    if (r >= 0) gy[O + r] += cmul_re(amp_lds[lds_at(r, HY)], qt1);
+                    gz[O + r] += cmul_re(amp_lds[lds_at(r, HZ)], qt0);
                 }
             }
         }
@@ -421,7 +470,7 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
         const bool st1 = q - 1 >= kb && q - 1 < ke;
         {
             float2 pt0, pt1;
-            phase(kq1, tE1, pt0, pt1);
+            phase(za0, za1, tE1, pt0, pt1);
 #pragma unroll
             for (int r = 0; r <= TY; ++r) {
                 const float hz_im = from_lower(gz[O + r]);
@@ -435,10 +484,9 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
                       gx[O + r] - gx[O + r - 1], RX(qe_yx, r), RX(qe_zx, r), RY(qe_xy, r),
                       RY(qe_zy, r), r < TY);
                 if (slot[O + r] >= 0) {
-                    const gptr<const float2> a = amp + (size_t)slot[O + r] * 6;
-                    fx[O + r] += cmul_re(ld2(a, EX), pt0);
-                    fz[O + r] += cmul_re(ld2(a, EZ), pt1);
-                    if (r < TY) fy[O + r] += cmul_re(ld2(a, EY), pt0);
+                    fx[O + r] += cmul_re(amp_lds[lds_at(r, EX)], pt0);
+                    fz[O + r] += cmul_re(amp_lds[lds_at(r, EZ)], pt1);
+                    if (r < TY) fy[O + r] += cmul_re(amp_lds[lds_at(r, EY)], pt0);
                 }
                 zero_out(r, fx[O + r], fy[O + r], fz[O + r]);
             }
@@ -473,7 +521,7 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
         // ---- H^{n+5/2}(q-2), rows 0 .. TY-1 --------------------------------
         if (q - 2 >= kb && q - 2 < ke) {
             float2 qt0, qt1;
-            phase(kq2, tH1, qt0, qt1);
+            phase(zb0, zb1, tH1, qt0, qt1);
 #pragma unroll
             for (int r = 0; r < TY; ++r) {
                 const float ey_ip = from_upper(e2y[O + r]);
@@ -484,10 +532,9 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
                       e2x[O + r + 1] - e2x[O + r], RX(qh_yx, r), RX(qh_zx, r), RY(qh_xy, r),
                       RY(qh_zy, r), true);
                 if (slot[O + r] >= 0) {
-                    const gptr<const float2> a = amp + (size_t)slot[O + r] * 6;
-                    vx += cmul_re(ld2(a, HX), qt1);
-                    vy += cmul_re(ld2(a, HY), qt1);
-                    vz += cmul_re(ld2(a, HZ), qt0);
+                    vx += cmul_re(amp_lds[lds_at(r, HX)], qt1);
+                    vy += cmul_re(amp_lds[lds_at(r, HY)], qt1);
+                    vz += cmul_re(amp_lds[lds_at(r, HZ)], qt0);
                 }
                 if (own && row_st(r)) {
                     st(HX, kq2, r, vx);
@@ -544,9 +591,21 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
                 qh_zy[O + r] = ph_zy[O + r];
             }
         }
+        zb0 = za0;
+        zb1 = za1;
+        za0 = zq0;
+        za1 = zq1;
         kq2 = kq1;
         kq1 = kq;
         kq = kq + 1 == nz ? 0 : kq + 1;
+        if constexpr (PF) {
+#pragma unroll
+            for (int r = -2; r <= TY + 1; ++r) {
+                nhx[O + r] = ld(HX, kq, r);
+                nhz[O + r] = ld(HZ, kq, r);
+                if (r >= -1) nhy[O + r] = ld(HY, kq, r);
+            }
+        }
     }
 }
 
@@ -596,6 +655,12 @@ step2_batch_kernel(const Problem* __restrict__ probs, const int4* __restrict__ i
     step2_tile<TY, XB, YB>(p, n, par, seg, grp, kz & 0xffff, kz >> 16, m0, m1);
 }
 
+// LDS of the staged antenna amplitudes of one workgroup: the 4 TY + 3 rows
+// its wavefronts form, six components, 64 lanes (33 KiB at TY = 2).
+constexpr unsigned amp_lds_bytes(int ty) {
+    return (unsigned)((WAVES * ty + 3) * 6 * 64 * sizeof(float2));
+}
+
 // Segments and row groups whose tiles form only regular cells (an interval
 // each, possibly empty).
 struct Plan2 {
@@ -641,7 +706,8 @@ hipError_t launch_class(const Problem& p, long long n, int parity, const Launch2
     if (nt <= 0) return hipSuccess;
     const int nbp = (nt + 7) / 8 * 8;
     if (timer) timer->mark_on(name, s);
-    hipLaunchKernelGGL((step2_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES), 0, s, p, n,
+    hipLaunchKernelGGL((step2_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES),
+                       p.colmap ? amp_lds_bytes(TY) : 0, s, p, n,
                        parity, L, nbp, mask0, mask1);
     hipError_t e = hipGetLastError();
     if (timer) timer->mark_on(nullptr, s);
@@ -700,7 +766,8 @@ hipError_t launch_batch_class(const Problem* probs, const int4* items, int nitem
                               const long long* nctr, int off, int par, int diag, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     const int nbp = (nitems + 7) / 8 * 8;
-    hipLaunchKernelGGL((step2_batch_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES), 0, s,
+    hipLaunchKernelGGL((step2_batch_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES),
+                       amp_lds_bytes(TY), s,
                        probs, items, nitems, nbp, nctr, off, par, diag);
     return hipGetLastError();
 }

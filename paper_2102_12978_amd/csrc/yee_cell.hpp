@@ -157,9 +157,9 @@ __device__ __forceinline__ double e_point(const Problem& p, long long n, int par
     const int slot = p.colmap ? G(p.colmap)[(size_t)j * p.nx + i] : -1;
     float2 pt0 = make_float2(0.f, 0.f), pt1 = pt0;
     if (slot >= 0) {
-        const float2 t = ld2(G(p.tE), n);
-        pt0 = cmul(ld2(G(p.zph), 2 * k), t);
-        pt1 = cmul(ld2(G(p.zph), 2 * k + 1), t);
+        const float2 t = ldc2(p.tE, n);
+        pt0 = cmul(ldc2(p.zph, 2 * k), t);
+        pt1 = cmul(ldc2(p.zph, 2 * k + 1), t);
     }
     e_cell(p, par, i, j, k, h, ex, ey, ez, slot, pt0, pt1, true);
     fn(EX)[id] = ex;
@@ -208,9 +208,9 @@ __device__ __forceinline__ double h_point(const Problem& p, long long n, int par
     const int slot = p.colmap ? G(p.colmap)[(size_t)j * p.nx + i] : -1;
     float2 qt0 = make_float2(0.f, 0.f), qt1 = qt0;
     if (slot >= 0) {
-        const float2 t = ld2(G(p.tH), n);
-        qt0 = cmul(ld2(G(p.zph), 2 * k), t);
-        qt1 = cmul(ld2(G(p.zph), 2 * k + 1), t);
+        const float2 t = ldc2(p.tH, n);
+        qt0 = cmul(ldc2(p.zph, 2 * k), t);
+        qt1 = cmul(ldc2(p.zph, 2 * k + 1), t);
     }
     h_cell(p, par, i, j, k, e, hx, hy, hz, slot, qt0, qt1);
     fn(HX)[id] = hx;
