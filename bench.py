@@ -21,9 +21,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 BYTES_PER_CELL = 48            # read + write six FP32 field components
 CSRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc")
-# interior kernels: source file, committed PMC summary, cell-updates per cell and launch
+# interior kernels: source file, committed PMC summary (one per tile shape
+# where the name has {rows} and {zchunk}), cell-updates per cell and launch
 KERNELS = {
-    "step2_pass": ("kernels_step2.hip", "step2_pass_768x768x255_traffic.json", 2),
+    "step2_pass": ("kernels_step2.hip",
+                   "step2_pass_768x768x255_rows{rows}_z{zchunk}_traffic.json", 2),
     "fused_interior": ("kernels_fused.hip", "fused_interior_768x768x255_traffic.json", 1),
 }
 
@@ -37,14 +39,23 @@ def kernel_hash(name):
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(name):
+def measured_traffic(name, tile=None):
     """HBM bytes per launch of an interior kernel from the committed
-    rocprofv3 PMC summary, or None when missing or taken on another source."""
+    rocprofv3 PMC summary of its tile shape (rows, z chunk), or None when
+    there is none or it was taken on another source."""
+    fname = KERNELS[name][1]
+    if "{" in fname:
+        if not tile:
+            return None
+        fname = fname.format(rows=tile[0], zchunk=tile[1])
     try:
-        t = json.load(open(os.path.join(ROOT, "profiles", KERNELS[name][1])))
+        t = json.load(open(os.path.join(ROOT, "profiles", fname)))
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha256_16") != kernel_hash(name):
+        return None
+    rec = t.get("tile")
+    if rec and tile and (rec["rows"], rec["zchunk"]) != tuple(tile):
         return None
     return t.get("bytes_per_launch")
 
@@ -128,7 +139,7 @@ def cpu_baseline(full=False):
             "legs": out}
 
 
-def batch_measure(torch, stream, steps=1000, warmup=20, graph_steps=20):
+def batch_measure(torch, stream, steps=1000, warmup=20, graph_steps=20, tile=None):
     """The 64-instance seed-1 sweep: autotuned work shape, 20-step graphs,
     mid-plane ⟨E_y²⟩ over the last 5 periods of each instance, then the
     per-instance deviation from the analytic beam (report only)."""
@@ -138,7 +149,12 @@ def batch_measure(torch, stream, steps=1000, warmup=20, graph_steps=20):
     from paper_2102_12978_amd.batch import Batch
     ws = W.batch64_instances()
     b = Batch(ws, stream=stream.cuda_stream)
-    cols, zc = b.autotune(3)
+    if tile:
+        # a fixed two-step tile (profiling runs: the same launches every run)
+        cols, zc = None, None
+        b.set_time_block(2, tile[0], tile[1])
+    else:
+        cols, zc = b.autotune(3)
     b.set_graph_steps(graph_steps)
     total = warmup + steps
     for q, w in enumerate(ws):
@@ -353,6 +369,9 @@ def main():
                     help="steps per captured graph in the batch leg (0: eager launches)")
     ap.add_argument("--no-step", action="store_true",
                     help="skip the single-domain leg (profiling runs of the other legs)")
+    ap.add_argument("--batch-tile", default=None,
+                    help="ROWS,ZCHUNK: run the batch with the two-step kernel at this tile "
+                         "instead of autotuning")
     ap.add_argument("--shard", type=int, default=8,
                     help="also time one GPU's z-slab share of the grid cut into this many "
                          "slabs (0: skip)")
@@ -444,7 +463,8 @@ def main():
             int_gbs = int_bytes / (int_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("step2_pass"), "kernel": "step2_pass",
+                    "traffic": measured_traffic("step2_pass", (info.tb_rows, info.tb_zchunk)),
+                    "kernel": "step2_pass",
                     "launch": "one two-step pass: interior, x-boundary, y-boundary and corner "
                               "tile launches, " + ("one after another" if args.sequential_classes
                                                    else "concurrent"),
@@ -516,7 +536,9 @@ def main():
         log(f"[bench] shard: {out['shard']}")
     if not args.no_batch:
         log("[bench] 64-instance batch ...")
-        out["batch"] = batch_measure(torch, stream, graph_steps=args.batch_graph_steps)
+        tile = tuple(int(v) for v in args.batch_tile.split(",")) if args.batch_tile else None
+        out["batch"] = batch_measure(torch, stream, graph_steps=args.batch_graph_steps,
+                                     tile=tile)
         log(f"[bench] batch: {out['batch']['value']} Gcell/s")
     if not args.no_adjoint:
         log("[bench] adjoint gradient cost ...")

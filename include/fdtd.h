@@ -357,7 +357,7 @@ int fdtd_set_concurrency(fdtd_ctx *ctx, int32_t on);
  * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
  * frames, and, except in the periodic test mode, the two-step kernel
  * (fdtd_set_time_block) at rows {4, 2} x z chunks {nz/8, nz/16, nz/4,
- * whole} (rounded up). Each
+ * nz/2, whole} (rounded up, repeats dropped). Each
  * candidate is timed over at least steps_per_trial steps, and over more
  * until the timed span reaches about 2 ms. One-step trials read what the
  * previous trial wrote, as a run does: they go back and forth between the
@@ -567,7 +567,7 @@ int fdtd_batch_set_graph_steps(fdtd_batch *b, int32_t steps);
 /* Time every kernel and work-item shape (fused with zchunk in
  * {0, 32, 16, 8}; split with cols x zchunk in {64, 128, 256} x
  * {0, 16, 8, 4, 1}; and, without periodic instances, the two-step kernel at
- * rows {2, 4} x zchunk {16, 32, 8}) for steps_per_trial steps on the live
+ * rows {2, 4} x zchunk {16, 32, 8, 0}) for steps_per_trial steps on the live
  * state and keep the fastest (fdtd_batch_get_info reports whether the
  * two-step kernel won); *best_cols is 0 when the fused kernel wins among the
  * one-step kernels, which odd steps use. Trials write only the buffers of

@@ -454,7 +454,7 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
         if (!periodic) {
             const int rows0 = b->tb_rows, zc0 = b->tb_zchunk;
             for (int rows : {2, 4})
-                for (int zc : {16, 32, 8}) {
+                for (int zc : {16, 32, 8, 0}) {
                     b->tb_rows = rows;
                     b->tb_zchunk = zc;
                     build_items2(b);

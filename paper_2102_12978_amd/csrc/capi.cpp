@@ -790,8 +790,11 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
             c->time_block = 2;
             // 8 or 16 chunks (each XCD then marches whole chunk layers of
-            // tiles), 4, and the whole z
-            std::vector<int> chunks2 = {(nz + 7) / 8, (nz + 15) / 16, (nz + 3) / 4, 0};
+            // tiles), 4, 2 (short grids: z slabs), and the whole z
+            std::vector<int> chunks2;
+            for (int cz : {(nz + 7) / 8, (nz + 15) / 16, (nz + 3) / 4, (nz + 1) / 2, 0})
+                if (std::find(chunks2.begin(), chunks2.end(), cz) == chunks2.end())
+                    chunks2.push_back(cz);
             for (int rows : {4, 2}) {
                 for (int cz : chunks2) {
                     if (cz > nz) continue;

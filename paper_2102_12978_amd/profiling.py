@@ -197,6 +197,9 @@ def traffic_sum(a):
         "bytes_per_launch": round(rd + wr),
         "cells_per_launch": a.cells,
         "bytes_per_cell": round((rd + wr) / a.cells, 2) if a.cells else None,
+        # the tile shape the counters were taken with (rows, z chunk)
+        "tile": ({"rows": int(a.tile.split(",")[0]), "zchunk": int(a.tile.split(",")[1])}
+                 if a.tile else None),
     }
 
 
@@ -227,6 +230,7 @@ def main(argv=None):
     g.add_argument("--copy-bytes", dest="copy_bytes", type=int, required=True)
     g.add_argument("--cells", type=int, default=0)
     g.add_argument("--row", action="append", required=True, help="KERNEL[@GRID]")
+    g.add_argument("--tile", default=None, help="ROWS,ZCHUNK of the profiled launches")
     a = ap.parse_args(argv)
     if a.what == "sum":
         print(json.dumps(traffic_sum(a), indent=1))
