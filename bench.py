@@ -154,7 +154,7 @@ def batch_measure(torch, stream, steps=1000, warmup=20, graph_steps=20, tile=Non
         cols, zc = None, None
         b.set_time_block(2, tile[0], tile[1])
     else:
-        cols, zc = b.autotune(3)
+        cols, zc = b.autotune(10)
     b.set_graph_steps(graph_steps)
     total = warmup + steps
     for q, w in enumerate(ws):

@@ -269,6 +269,14 @@ def parity_mid():
                     ramp_periods=2.0)
 
 
+def parity_thick():
+    """A thick antenna filling whole tiles: 200×180×(16 hint), 10-cell CPML,
+    θ = 25°, m = 2, Δx = λ/14, annulus from r = 40 to R_B = 78 cells (two
+    cells short of the y CPML, reaching x- and y-boundary tiles), 30 steps."""
+    return Workload("p_thick_200x180x16_theta25_m2", 200, 180, 16, 14.0, 25.0, 2, 78.0, 38.0, 10,
+                    30, ramp_periods=2.0)
+
+
 def parity_wide():
     """Seven fused segments (two workgroups of four x-adjacent wavefronts, the
     second one short): 540×80×(16 hint), 10-cell CPML, θ = 22°, m = 1,

@@ -144,6 +144,26 @@ def test_against_oracle():
     s.close()
 
 
+@pytest.mark.parametrize("rows,zchunk", [(2, 0), (4, 5)])
+def test_thick_antenna_fills_tiles(rows, zchunk):
+    """An annulus 38 cells thick reaching the x- and y-boundary tiles: whole
+    tiles take the source on every lane and row, so every stage reads its
+    amplitudes from the tile's LDS copy. The two-step run equals the
+    one-step run bit for bit, and (rows 2) the FP64 oracle within the parity
+    bars."""
+    w = W.parity_thick()
+    one, two = _solvers(w, rows, zchunk)
+    assert one.info().n_slots > 10000
+    for s in (one, two):
+        s.step(w.steps)
+    _assert_identical(one, two, w, f"thick antenna rows={rows} zchunk={zchunk}")
+    if rows == 2:
+        g, st = GC.oracle_run(w, w.steps)
+        GC.assert_parity(two.fields(), [st.f[c] for c in GC.COMPS], "thick antenna, two-step")
+    one.close()
+    two.close()
+
+
 def test_fallbacks():
     """Energy diagnostic on and the split kernel: pairs run as single steps,
     with the same results; a grid with no wall-free tile runs pairs through
