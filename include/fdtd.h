@@ -571,7 +571,9 @@ int fdtd_batch_set_graph_steps(fdtd_batch *b, int32_t steps);
  * state and keep the fastest (fdtd_batch_get_info reports whether the
  * two-step kernel won); *best_cols is 0 when the fused kernel wins among the
  * one-step kernels, which odd steps use. Trials write only the buffers of
- * the next parity, so the state is unchanged. */
+ * the next parity, so the state is unchanged; while the batch steps from
+ * graphs (fdtd_batch_set_graph_steps > 0) each trial's launches are
+ * captured into a graph and replayed, as a run replays its steps. */
 int fdtd_batch_autotune(fdtd_batch *b, int32_t steps_per_trial, int32_t *best_cols,
                         int32_t *best_zchunk);
 
