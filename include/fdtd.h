@@ -334,10 +334,9 @@ int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
  * two-step kernel over the whole grid (the Yee update of §4 with its CPML
  * and soft source applied twice in registers: each field and CPML memory
  * is read and written once per pair, 24 B of fields per cell-update), on
- * tiles of 60 x cells by `rows` (2 or 4) rows per wavefront (tiles at the
- * y walls and corners: 2) marching through z chunks of zchunk planes (0 =
- * the whole z; corner and y-wall tiles take at most 8 and 16 planes);
- * tiles free of walls and CPML, tiles at the x walls, at
+ * tiles of 60 x cells by `rows` (2 or 4) rows marching through z chunks of
+ * zchunk planes (0 = the whole z; corner and y-wall tiles take at most 8
+ * and 16 planes); tiles free of walls and CPML, tiles at the x walls, at
  * the y walls and at the corners run as four launches, the three boundary
  * ones on streams the context creates, concurrent with the interior one
  * (forked from and joined back into the context's stream by events). No
@@ -572,9 +571,7 @@ int fdtd_batch_set_graph_steps(fdtd_batch *b, int32_t steps);
  * state and keep the fastest (fdtd_batch_get_info reports whether the
  * two-step kernel won); *best_cols is 0 when the fused kernel wins among the
  * one-step kernels, which odd steps use. Trials write only the buffers of
- * the next parity, so the state is unchanged; while the batch steps from
- * graphs (fdtd_batch_set_graph_steps > 0) each trial's launches are
- * captured into a graph and replayed, as a run replays its steps. */
+ * the next parity, so the state is unchanged. */
 int fdtd_batch_autotune(fdtd_batch *b, int32_t steps_per_trial, int32_t *best_cols,
                         int32_t *best_zchunk);
 

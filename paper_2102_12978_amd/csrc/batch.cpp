@@ -411,16 +411,9 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
         need(steps_per_trial >= 1 && steps_per_trial <= 1000, "steps_per_trial out of range");
         for (fdtd_ctx* c : b->inst) ensure_time_tables(c, b->step + 1);
         upload_problems(b);
-        struct Events {   // destroyed however the trials end
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            ~Events() {
-                if (e0) (void)hipEventDestroy(e0);
-                if (e1) (void)hipEventDestroy(e1);
-            }
-        } ev;
-        check(hipEventCreate(&ev.e0), "event");
-        check(hipEventCreate(&ev.e1), "event");
-        const hipEvent_t e0 = ev.e0, e1 = ev.e1;
+        hipEvent_t e0, e1;
+        check(hipEventCreate(&e0), "event");
+        check(hipEventCreate(&e1), "event");
         int bk = b->kernel, bc = b->cols, bz = b->zchunk, br = b->bnd_rows;
         float best = -1.f;
         struct Cand { int kernel, cols, zc, rows; };
@@ -429,53 +422,22 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
             for (int zc : {0, 32, 16, 8}) cands.push_back({FDTD_KERNEL_FUSED, b->cols, zc, rows});
         for (int cols : {64, 128, 256})
             for (int zc : {0, 16, 8, 4, 1}) cands.push_back({FDTD_KERNEL_SPLIT, cols, zc, br});
-        // Milliseconds of `calls` trial launches after one untimed: replayed
-        // from one captured graph when the batch steps from graphs (the
-        // launches then run as a stepping run's do), else launched one by
-        // one. Trials read the live parity and write the other one only,
-        // with the plane accumulation off, so the state is left as it was.
-        auto timed = [&](auto&& launch, int calls) {
-            if (b->graph_steps > 0) {
-                hipGraph_t g = nullptr;
-                hipGraphExec_t ex = nullptr;
-                check(hipStreamBeginCapture(b->capture, hipStreamCaptureModeRelaxed),
-                      "begin capture");
-                hipError_t le = hipSuccess;
-                for (int t = 0; t < calls && le == hipSuccess; ++t) le = launch(b->capture);
-                const hipError_t ee = hipStreamEndCapture(b->capture, &g);
-                check(le, "captured trial");
-                check(ee, "end capture");
-                const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                check(ie, "graph instantiate");
-                hipError_t re = hipGraphLaunch(ex, b->stream);
-                if (re == hipSuccess) re = hipEventRecord(e0, b->stream);
-                if (re == hipSuccess) re = hipGraphLaunch(ex, b->stream);
-                if (re == hipSuccess) re = hipEventRecord(e1, b->stream);
-                const hipError_t se = hipStreamSynchronize(b->stream);
-                (void)hipGraphExecDestroy(ex);
-                check(re, "graph trial");
-                check(se, "sync");
-            } else {
-                check(launch(b->stream), "trial");
-                check(hipEventRecord(e0, b->stream), "event");
-                for (int t = 0; t < calls; ++t) check(launch(b->stream), "trial");
-                check(hipEventRecord(e1, b->stream), "event");
-                check(hipEventSynchronize(e1), "event sync");
-            }
-            float ms = 0.f;
-            check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-            return ms;
-        };
+        // Trials read the live parity and write the other one only, with the
+        // plane accumulation off, so the state is left as it was.
         for (const Cand& cd : cands) {
             b->kernel = cd.kernel;
             b->bnd_rows = cd.rows;
             b->cols = cd.cols;
             b->zchunk = cd.zc;
             build_work(b);
-            const float ms = timed(
-                [&](hipStream_t s) { return launch_pair(b, s, 0, b->parity, 0); },
-                steps_per_trial);
+            check(launch_pair(b, b->stream, 0, b->parity, 0), "trial");
+            check(hipEventRecord(e0, b->stream), "event");
+            for (int t = 0; t < steps_per_trial; ++t)
+                check(launch_pair(b, b->stream, 0, b->parity, 0), "trial");
+            check(hipEventRecord(e1, b->stream), "event");
+            check(hipEventSynchronize(e1), "event sync");
+            float ms = 0.f;
+            check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
             if (best < 0.f || ms < best) {
                 best = ms;
                 bk = cd.kernel;
@@ -496,9 +458,15 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
                     b->tb_rows = rows;
                     b->tb_zchunk = zc;
                     build_items2(b);
+                    check(launch_two(b, b->stream, 0, b->parity, 0), "trial");
                     const int pairs = std::max(1, steps_per_trial / 2);
-                    float ms = timed(
-                        [&](hipStream_t s) { return launch_two(b, s, 0, b->parity, 0); }, pairs);
+                    check(hipEventRecord(e0, b->stream), "event");
+                    for (int t = 0; t < pairs; ++t)
+                        check(launch_two(b, b->stream, 0, b->parity, 0), "trial");
+                    check(hipEventRecord(e1, b->stream), "event");
+                    check(hipEventSynchronize(e1), "event sync");
+                    float ms = 0.f;
+                    check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
                     ms *= (float)steps_per_trial / (float)(2 * pairs);
                     if (ms < best) {
                         best = ms;
@@ -510,6 +478,8 @@ int fdtd_batch_autotune(fdtd_batch* b, int32_t steps_per_trial, int32_t* best_co
             b->tb_rows = rows0;
             b->tb_zchunk = zc0;
         }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         b->kernel = bk;
         b->bnd_rows = br;
         b->cols = bc;

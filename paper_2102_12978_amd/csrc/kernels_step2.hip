@@ -91,11 +91,10 @@ __device__ __forceinline__ int span_at(const Span& s, int i) {
     return i < na ? s.a0 + i : s.b0 + (i - na);
 }
 
-// One launch: its x segments, its row groups (counted from row y0) and the
-// z chunks.
+// One launch: its x segments and row groups, and the z chunks.
 struct Launch2 {
     Span seg, grp;
-    int cz, ncz, y0;
+    int cz, ncz;
 };
 
 // CPML coefficients of one position: b, c and 1/κ (identity outside a slab).
@@ -109,15 +108,14 @@ constexpr int step2_waves() {
     return 2;
 }
 
-// One tile: x segment seg, row group grp of the groups counted from row y0,
-// planes [kb, ke) of problem p, advanced from step n (parity par) to n + 2.
+// One tile: x segment seg, row group grp, planes [kb, ke) of problem p,
+// advanced from step n (parity par) to n + 2.
 template <int TY, bool XB, bool YB>
 __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int par, int seg,
-                                           int grp, int y0, int kb, int ke, int mask0,
-                                           int mask1) {
+                                           int grp, int kb, int ke, int mask0, int mask1) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nz = p.nz, nx = p.nx, ny = p.ny;
-    const int j0 = y0 + (grp * WAVES + w) * TY;
+    const int j0 = (grp * WAVES + w) * TY;
     if (j0 >= ny) {                                            // uniform per wavefront
         for (int q = kb - 2; q <= ke + 1; ++q) __syncthreads(); // the others' barriers
         return;
@@ -625,8 +623,8 @@ step2_kernel(Problem p, long long n, int par, Launch2 L, int nblocks_padded, int
     if (lb >= ntile * L.ncz) return;
     const int t = lb % ntile;
     const int kb = (lb / ntile) * L.cz;
-    step2_tile<TY, XB, YB>(p, n, par, span_at(L.seg, t % nsl), span_at(L.grp, t / nsl), L.y0,
-                           kb, min(kb + L.cz, p.nz), mask0, mask1);
+    step2_tile<TY, XB, YB>(p, n, par, span_at(L.seg, t % nsl), span_at(L.grp, t / nsl), kb,
+                           min(kb + L.cz, p.nz), mask0, mask1);
 }
 
 // Many instances: one work item per workgroup, (instance, segment, row
@@ -654,7 +652,7 @@ step2_batch_kernel(const Problem* __restrict__ probs, const int4* __restrict__ i
     const long long n = *nctr + off;
     const int m0 = diag && p.plane >= 0 && n >= p.win_begin ? p.diag_mask : 0;
     const int m1 = diag && p.plane >= 0 && n + 1 >= p.win_begin ? p.diag_mask : 0;
-    step2_tile<TY, XB, YB>(p, n, par, seg, grp, 0, kz & 0xffff, kz >> 16, m0, m1);
+    step2_tile<TY, XB, YB>(p, n, par, seg, grp, kz & 0xffff, kz >> 16, m0, m1);
 }
 
 // LDS of the staged antenna amplitudes of one workgroup: the 4 TY + 3 rows
@@ -701,35 +699,6 @@ Plan2 plan2(const Problem& p, int rows, int zchunk) {
     return P;
 }
 
-// Rows of the single-domain launches when the interior and x-boundary tiles
-// hold TYI rows per wavefront and the y-boundary and corner tiles TYB (TYI a
-// multiple of TYB): the interior rows [ya, yb) start at the first multiple
-// of a y-boundary group (4 TYB rows) whose group forms regular rows only,
-// and hold whole groups of 4 TYI rows; the y-boundary groups (counted from
-// row 0) cover [0, ya) and [yb, ny).
-struct Rows2 {
-    int ya, ni;    // interior rows start at ya: ni groups of 4 TYI rows
-    Span gb;       // y-boundary groups of 4 TYB rows, from row 0
-};
-
-Rows2 rows_plan(const Problem& p, int tyi, int tyb) {
-    const int gi = WAVES * tyi, gbh = WAVES * tyb;
-    const int m = std::max(p.npml, 1);
-    const int ngb = (p.ny + gbh - 1) / gbh;
-    Rows2 r{};
-    r.ya = (m + 1 + gbh - 1) / gbh * gbh;
-    const int room = p.ny - p.npml - 2 - gi - r.ya;   // last group: gy + gi + 1 <= ny - npml - 1
-    r.ni = room >= 0 ? room / gi + 1 : 0;
-    if (r.ni == 0) {
-        r.ya = 0;
-        r.gb = Span{0, ngb, 0, 0};
-        return r;
-    }
-    const int yb = r.ya + r.ni * gi;
-    r.gb = Span{0, r.ya / gbh, yb / gbh, ngb};
-    return r;
-}
-
 template <int TY, bool XB, bool YB>
 hipError_t launch_class(const Problem& p, long long n, int parity, const Launch2& L, int mask0,
                         int mask1, hipStream_t s, LaunchTimer* timer, const char* name) {
@@ -748,15 +717,12 @@ hipError_t launch_class(const Problem& p, long long n, int parity, const Launch2
 // The four classes touch disjoint cells: with side streams the boundary
 // classes run beside the interior launch, forked from and joined back into
 // s by events (a per-launch timer brackets each kernel on its own stream).
-// Interior and x-boundary tiles hold TYI rows per wavefront, y-boundary and
-// corner tiles TYB.
-template <int TYI, int TYB>
+template <int TY>
 hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, int mask0,
                        int mask1, hipStream_t s, LaunchTimer* timer, const SideStreams* side) {
-    const Plan2 P = plan2(p, TYI, zchunk);   // segments and z chunks
-    const Rows2 Y = rows_plan(p, TYI, TYB);
+    const Plan2 P = plan2(p, TY, zchunk);
     const Span s_int{P.s_lo, P.s_hi, 0, 0}, s_bnd{0, P.s_lo, P.s_hi, P.nseg};
-    const Span g_int{0, Y.ni, 0, 0};
+    const Span g_int{P.g_lo, P.g_hi, 0, 0}, g_bnd{0, P.g_lo, P.g_hi, P.ngrp};
     const bool fork = side != nullptr;
     hipStream_t sx = s, sy = s, sc = s;
     hipError_t e;
@@ -772,21 +738,19 @@ hipError_t launch_rows(const Problem& p, long long n, int parity, int zchunk, in
     // give them more workgroups (and a shorter critical path) at the cost
     // of re-reading two planes at each chunk end.
     const int czc = std::min(P.cz, 8), czy = std::min(P.cz, 16);
-    e = launch_class<TYB, true, true>(p, n, parity,
-                                      Launch2{s_bnd, Y.gb, czc, (p.nz + czc - 1) / czc, 0},
-                                      mask0, mask1, sc, timer, "step2_corner");
+    e = launch_class<TY, true, true>(p, n, parity,
+                                     Launch2{s_bnd, g_bnd, czc, (p.nz + czc - 1) / czc}, mask0,
+                                     mask1, sc, timer, "step2_corner");
     if (e == hipSuccess)
-        e = launch_class<TYB, false, true>(p, n, parity,
-                                           Launch2{s_int, Y.gb, czy, (p.nz + czy - 1) / czy, 0},
-                                           mask0, mask1, sy, timer, "step2_ybnd");
+        e = launch_class<TY, false, true>(p, n, parity,
+                                          Launch2{s_int, g_bnd, czy, (p.nz + czy - 1) / czy},
+                                          mask0, mask1, sy, timer, "step2_ybnd");
     if (e == hipSuccess)
-        e = launch_class<TYI, true, false>(p, n, parity,
-                                           Launch2{s_bnd, g_int, P.cz, P.ncz, Y.ya}, mask0,
-                                           mask1, sx, timer, "step2_xbnd");
+        e = launch_class<TY, true, false>(p, n, parity, Launch2{s_bnd, g_int, P.cz, P.ncz}, mask0,
+                                          mask1, sx, timer, "step2_xbnd");
     if (e == hipSuccess)
-        e = launch_class<TYI, false, false>(p, n, parity,
-                                            Launch2{s_int, g_int, P.cz, P.ncz, Y.ya}, mask0,
-                                            mask1, s, timer, "step2_interior");
+        e = launch_class<TY, false, false>(p, n, parity, Launch2{s_int, g_int, P.cz, P.ncz}, mask0,
+                                           mask1, s, timer, "step2_interior");
     if (fork) {
         for (int q = 0; q < 3; ++q) {
             hipError_t f = hipEventRecord(side->join[q], side->s[q]);
@@ -846,10 +810,9 @@ hipError_t launch_batch_rows(const Problem* probs, const int4* const items[4],
 
 long long step2_interior_cells(const Problem& p, int rows) {
     const Plan2 P = plan2(p, rows, 0);
-    const Rows2 Y = rows_plan(p, rows, 2);
-    if (P.s_lo >= P.s_hi || Y.ni == 0) return 0;
+    if (P.s_lo >= P.s_hi || P.g_lo >= P.g_hi) return 0;
     const long long xs = std::min(OWN * P.s_hi, p.nx) - OWN * P.s_lo;
-    const long long ys = (long long)WAVES * rows * Y.ni;
+    const long long ys = std::min(WAVES * rows * P.g_hi, p.ny) - WAVES * rows * P.g_lo;
     return xs * ys * p.nz;
 }
 
@@ -857,8 +820,8 @@ hipError_t launch_step2(const Problem& p, long long n, int parity, int rows, int
                         int mask0, int mask1, hipStream_t s, LaunchTimer* timer,
                         const SideStreams* side) {
     if (p.periodic) return hipErrorInvalidValue;
-    if (rows == 2) return launch_rows<2, 2>(p, n, parity, zchunk, mask0, mask1, s, timer, side);
-    if (rows == 4) return launch_rows<4, 2>(p, n, parity, zchunk, mask0, mask1, s, timer, side);
+    if (rows == 2) return launch_rows<2>(p, n, parity, zchunk, mask0, mask1, s, timer, side);
+    if (rows == 4) return launch_rows<4>(p, n, parity, zchunk, mask0, mask1, s, timer, side);
     return hipErrorInvalidValue;
 }
 
