@@ -26,6 +26,8 @@ CSRC = os.path.join(ROOT, "paper_2102_12978_amd", "csrc")
 KERNELS = {
     "step2_pass": ("kernels_step2.hip",
                    "step2_pass_768x768x255_rows{rows}_z{zchunk}_traffic.json", 2),
+    "step3_pass": ("kernels_step3.hip",
+                   "step3_pass_768x768x255_rows{rows}_z{zchunk}_traffic.json", 3),
     "fused_interior": ("kernels_fused.hip", "fused_interior_768x768x255_traffic.json", 1),
 }
 
@@ -277,8 +279,8 @@ def shard_measure(torch, stream, parts, steps=1000, warmup=20, reps=5):
         "ms_per_step": round(ms, 5),
         "value": round(cells / (ms * 1e-3) / 1e9, 2), "unit": "Gcell-updates/s",
         "steps_per_pass": it.time_block,
-        "tile_rows": it.tb_rows if it.time_block == 2 else it.tile_rows,
-        "tile_zchunk": it.tb_zchunk if it.time_block == 2 else it.tile_zchunk,
+        "tile_rows": it.tb_rows if it.time_block >= 2 else it.tile_rows,
+        "tile_zchunk": it.tb_zchunk if it.time_block >= 2 else it.tile_zchunk,
         "halo_bytes_per_pass_from_below": 8 * plane_bytes,
         "halo_bytes_per_pass_from_above": 11 * plane_bytes,
     }
@@ -355,9 +357,9 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="fix the tile rows (skips autotune)")
     ap.add_argument("--zchunk", type=int, default=0, help="z chunk with --rows")
     ap.add_argument("--time-block", type=int, default=0,
-                    help="fix the steps per interior pass (1 or 2)")
-    ap.add_argument("--tb-rows", type=int, default=4, help="two-step kernel rows")
-    ap.add_argument("--tb-zchunk", type=int, default=32, help="two-step kernel z chunk")
+                    help="fix the steps per pass (1, 2 or 3)")
+    ap.add_argument("--tb-rows", type=int, default=4, help="two-/three-step kernel rows")
+    ap.add_argument("--tb-zchunk", type=int, default=32, help="two-/three-step kernel z chunk")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient timing")
     ap.add_argument("--adjoint-reps", type=int, default=3,
@@ -405,7 +407,7 @@ def main():
             rows, zc = s.autotune(3)
             it = s.info()
             log(f"[bench] autotuned: one-step tile rows={rows} zchunk={zc}; steps per pass "
-                f"{it.time_block} (two-step tile rows={it.tb_rows} zchunk={it.tb_zchunk})")
+                f"{it.time_block} (multi-step tile rows={it.tb_rows} zchunk={it.tb_zchunk})")
         if args.time_block:
             s.set_time_block(args.time_block, args.tb_rows, args.tb_zchunk)
         if args.sequential_classes:
@@ -444,30 +446,34 @@ def main():
         log(f"[bench] kernels: {prof}")
 
         roof = None
-        if info.time_block == 2 and "step2_interior" in prof:
-            # Two-step passes: the four tile-class launches of a pass run
-            # concurrently (the boundary classes on side streams) and the
-            # interior launch spans the pass, so the unit is the pass: 48 B per
-            # cell-update, two updates of every cell, over the pass time of
-            # the timed runs (events on the solver's stream, which forks and
-            # joins the side streams). The per-kernel figures come from one
+        tb = info.time_block
+        if tb in (2, 3) and f"step{tb}_interior" in prof:
+            # Two- and three-step passes: the four tile-class launches of a
+            # pass run concurrently (the boundary classes on side streams)
+            # and the interior launch spans the pass, so the unit is the
+            # pass: 48 B per cell-update, tb updates of every cell, over the
+            # pass time of the timed runs (events on the solver's stream,
+            # which forks and joins the side streams; a remainder of steps
+            # that is not a whole pass runs as a shorter one and is counted
+            # at the same rate per step). The per-kernel figures come from one
             # more run of the same passes with an event pair around each
             # launch on its own stream.
-            pass_ms = total_ms / (args.steps / 2)
-            upd = 2 * cells
+            kname = f"step{tb}_pass"
+            pass_ms = total_ms / (args.steps / tb)
+            upd = tb * cells
             bytes_launch = BYTES_PER_CELL * upd
             achieved = bytes_launch / (pass_ms * 1e-3) / 1e9
-            ki = prof["step2_interior"]
+            ki = prof[f"step{tb}_interior"]
             int_ms = ki[1] / ki[0]
-            int_bytes = BYTES_PER_CELL * 2 * info.interior_cells
+            int_bytes = BYTES_PER_CELL * tb * info.interior_cells
             int_gbs = int_bytes / (int_ms * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("step2_pass", (info.tb_rows, info.tb_zchunk)),
-                    "kernel": "step2_pass",
-                    "launch": "one two-step pass: interior, x-boundary, y-boundary and corner "
-                              "tile launches, " + ("one after another" if args.sequential_classes
-                                                   else "concurrent"),
+                    "traffic": measured_traffic(kname, (info.tb_rows, info.tb_zchunk)),
+                    "kernel": kname,
+                    "launch": f"one {'two' if tb == 2 else 'three'}-step pass: interior, "
+                              "x-boundary, y-boundary and corner tile launches, " +
+                              ("one after another" if args.sequential_classes else "concurrent"),
                     "avg_launch_ms": round(pass_ms, 5), "cells_per_launch": cells,
                     "cell_updates_per_launch": upd,
                     "algorithmic_bytes_per_launch": bytes_launch,
@@ -475,10 +481,10 @@ def main():
                     # written once, whatever the steps it advances
                     "min_bytes_per_launch": BYTES_PER_CELL * cells,
                     "launches_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()
-                                    if k.startswith("step2_")},
+                                    if k.startswith(f"step{tb}_")},
                     "interior_launch": {
                         "avg_ms": round(int_ms, 5), "cells": info.interior_cells,
-                        "cell_updates": 2 * info.interior_cells,
+                        "cell_updates": tb * info.interior_cells,
                         "achieved": round(int_gbs, 1),
                         "frac": round(int_gbs / HBM_PEAK_GBS, 4)}}
         else:
@@ -523,8 +529,8 @@ def main():
                                    "theta=20deg, order-2 Bessel antenna R=320dx, 16-cell CPML",
                        "cells": cells, "steps_per_pass": info.time_block,
                        "classes_concurrent": not args.sequential_classes,
-                       "tile_rows": info.tb_rows if info.time_block == 2 else info.tile_rows,
-                       "tile_zchunk": info.tb_zchunk if info.time_block == 2 else info.tile_zchunk},
+                       "tile_rows": info.tb_rows if info.time_block >= 2 else info.tile_rows,
+                       "tile_zchunk": info.tb_zchunk if info.time_block >= 2 else info.tile_zchunk},
             "step_hbm_fraction": round(step_gbs / HBM_PEAK_GBS, 4),
             "kernels_ms": {k: round(v[1] / v[0], 5) for k, v in prof.items()},
             "roofline": roof,

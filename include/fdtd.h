@@ -158,9 +158,9 @@ typedef struct fdtd_info {
     int32_t frame;               /* FDTD_FRAME_* used around the interior     */
     int32_t xalign;              /* interior x origin multiple (32 or 64)     */
     int32_t frame_rows;          /* rows per fused frame tile (2 or 4)        */
-    int32_t time_block;          /* steps per interior pass (1 or 2)          */
-    int32_t tb_rows;             /* two-step kernel: y rows per wavefront     */
-    int32_t tb_zchunk;           /* two-step kernel: z planes per chunk       */
+    int32_t time_block;          /* steps per pass (1, 2 or 3)                */
+    int32_t tb_rows;             /* 2-/3-step kernel: y rows per wavefront    */
+    int32_t tb_zchunk;           /* 2-/3-step kernel: z planes per chunk      */
 } fdtd_info;
 
 /* Library version string (static storage). */
@@ -221,8 +221,8 @@ int fdtd_create_ext(const fdtd_grid *grid, float *const dev_fields[2], fdtd_ctx 
 /* Device address of the parity buffer that holds the current state
  * (E^n and H̃^{n+1/2} after n steps; six components in the fdtd_field_layout
  * layout): one of the two buffers of fdtd_create_ext, or a library-owned one.
- * It changes with every step call (a two-step pass flips the parity once per
- * pair), so query it after stepping; the contents are complete once the
+ * It changes with every step call (a two- or three-step pass flips the
+ * parity once per pass), so query it after stepping; the contents are complete once the
  * grid's stream has finished the steps. */
 int fdtd_current_fields(const fdtd_ctx *ctx, float **dev_ptr);
 
@@ -343,10 +343,15 @@ int fdtd_set_frame(fdtd_ctx *ctx, int32_t kind, int32_t xalign, int32_t rows);
  * buffer is allocated. The result is bit-identical to one-step runs. Pairs
  * fall back to single steps for the split kernel choice, the periodic test
  * mode, and while the energy diagnostic or a plane record is on; an odd
- * last step runs alone. */
+ * last step runs alone. steps = 3: triples of steps run the three-step
+ * kernel (the update applied three times in registers, 16 B of fields per
+ * cell-update) on tiles of 58 x cells by `rows` rows in the same four
+ * launches and under the same fallbacks; a remainder of two steps runs as a
+ * pair through the two-step kernel, one step alone. Other values:
+ * FDTD_EINVAL. */
 int fdtd_set_time_block(fdtd_ctx *ctx, int32_t steps, int32_t rows, int32_t zchunk);
 
-/* Whether the two-step kernel's three boundary launches run beside the
+/* Whether the two- and three-step kernels' three boundary launches run beside the
  * interior one on the context's side streams (on = 1, the default) or one
  * after another on the context's stream (on = 0), for example to time each
  * launch alone with fdtd_profile_enable. Results are the same bit for bit
@@ -355,9 +360,9 @@ int fdtd_set_concurrency(fdtd_ctx *ctx, int32_t on);
 
 /* Time candidate tile shapes and frame choices on the live problem (the state
  * is restored) and keep the fastest: the one-step kernel's rows x z chunks x
- * frames, and, except in the periodic test mode, the two-step kernel
- * (fdtd_set_time_block) at rows {4, 2} x z chunks {nz/8, nz/16, nz/4,
- * nz/2, whole} (rounded up, repeats dropped). Each
+ * frames, and, except in the periodic test mode, the two-step and the
+ * three-step kernels (fdtd_set_time_block) at rows {4, 2} x z chunks {nz/8,
+ * nz/16, nz/4, nz/2, whole} (rounded up, repeats dropped). Each
  * candidate is timed over at least steps_per_trial steps, and over more
  * until the timed span reaches about 2 ms. One-step trials read what the
  * previous trial wrote, as a run does: they go back and forth between the
@@ -365,7 +370,7 @@ int fdtd_set_concurrency(fdtd_ctx *ctx, int32_t on);
  * allocates and frees (when the device lacks the memory, each trial re-runs
  * the same step from the live state instead). *best_rows / *best_zchunk (may
  * be NULL) receive the one-step kernel's tile; fdtd_get_info reports
- * whether the two-step kernel won (time_block) and its tile. */
+ * whether the two- or three-step kernel won (time_block) and its tile. */
 int fdtd_autotune(fdtd_ctx *ctx, int32_t steps_per_trial, int32_t *best_rows,
                   int32_t *best_zchunk);
 

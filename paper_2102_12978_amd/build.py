@@ -17,7 +17,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Wall", "-Wno-unused-function"]
 SOURCES = ["host_setup.cpp", "capi.cpp", "batch.cpp", "adjoint.cpp", "kernels_split.hip",
            "kernels_fused.hip", "kernels_fused_bnd.hip", "kernels_batch.hip",
-           "kernels_adjoint.hip", "kernels_probe.hip", "kernels_step2.hip",
+           "kernels_adjoint.hip", "kernels_probe.hip", "kernels_step2.hip", "kernels_step3.hip",
            "step_static.hip"]
 
 

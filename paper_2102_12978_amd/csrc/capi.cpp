@@ -370,9 +370,12 @@ int fdtd_step(fdtd_ctx* c, int64_t nsteps) {
         need(nsteps >= 0, "nsteps must be >= 0");
         ensure_time_tables(c, c->step + nsteps);
         ensure_partials(c);
-        const bool pairs = two_step_on(c);
+        const bool pairs = two_step_on(c), triples = three_step_on(c);
         for (int64_t s = 0; s < nsteps;) {
-            if (pairs && nsteps - s >= 2) {
+            if (triples && nsteps - s >= 3) {
+                launch_triple(c, c->step);
+                s += 3;
+            } else if (pairs && nsteps - s >= 2) {
                 launch_pair(c, c->step);
                 s += 2;
             } else {
@@ -536,7 +539,9 @@ int fdtd_get_info(const fdtd_ctx* c, fdtd_info* out) {
     out->tb_zchunk = c->tb_zchunk;
     out->step = c->step;
     out->device_bytes = c->device_bytes;
-    if (two_step_on(c)) {
+    if (three_step_on(c)) {
+        out->interior_cells = step3_interior_cells(c->p, c->tb_rows);
+    } else if (two_step_on(c)) {
         out->interior_cells = step2_interior_cells(c->p, c->tb_rows);
     } else {
         const Frame fr = interior_of(c);
@@ -587,7 +592,7 @@ int fdtd_set_time_block(fdtd_ctx* c, int32_t steps, int32_t rows, int32_t zchunk
         return FDTD_ESTATE;
     }
     return guarded(c, [&] {
-        need(steps == 1 || steps == 2, "steps must be 1 or 2");
+        need(steps >= 1 && steps <= 3, "steps must be 1, 2 or 3");
         need(rows == 2 || rows == 4, "rows must be 2 or 4");
         need(zchunk >= 0 && zchunk <= c->p.nz, "zchunk out of range");
         c->time_block = steps;
@@ -783,11 +788,12 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
         c->xalign = ba;
         c->frame_rows = bfr;
         ensure_partials(c);
-        // the two-step kernel (per step: half a pair)
+        // the two- and three-step kernels (per step: half a pair, a third of
+        // a triple)
         const bool try2 = !c->p.periodic;
         int bt = 1, btr = c->tb_rows, btz = c->tb_zchunk;
         if (try2) {
-            c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs
+            c->mask &= ~(unsigned)FDTD_DIAG_ENERGY;   // the trials run pairs and triples
             c->time_block = 2;
             // 8 or 16 chunks (each XCD then marches whole chunk layers of
             // tiles), 4, 2 (short grids: z slabs), and the whole z
@@ -795,17 +801,23 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             for (int cz : {(nz + 7) / 8, (nz + 15) / 16, (nz + 3) / 4, (nz + 1) / 2, 0})
                 if (std::find(chunks2.begin(), chunks2.end(), cz) == chunks2.end())
                     chunks2.push_back(cz);
-            for (int rows : {4, 2}) {
-                for (int cz : chunks2) {
-                    if (cz > nz) continue;
-                    c->tb_rows = rows;
-                    c->tb_zchunk = cz;
-                    const float ms = per_step([&] { launch_pair(c, c->step, true); }, 2);
-                    if (ms < best) {
-                        best = ms;
-                        bt = 2;
-                        btr = rows;
-                        btz = cz;
+            for (int steps : {2, 3}) {
+                c->time_block = steps;
+                for (int rows : {4, 2}) {
+                    for (int cz : chunks2) {
+                        if (cz > nz) continue;
+                        c->tb_rows = rows;
+                        c->tb_zchunk = cz;
+                        const float ms =
+                            steps == 3
+                                ? per_step([&] { launch_triple(c, c->step, true); }, 3)
+                                : per_step([&] { launch_pair(c, c->step, true); }, 2);
+                        if (ms < best) {
+                            best = ms;
+                            bt = steps;
+                            btr = rows;
+                            btz = cz;
+                        }
                     }
                 }
             }
@@ -814,8 +826,8 @@ int fdtd_autotune(fdtd_ctx* c, int32_t steps_per_trial, int32_t* best_rows,
             c->tb_rows = rs.tb_rows;
             c->tb_zchunk = rs.tb_zchunk;
         }
-        if (bt == 2) {
-            c->time_block = 2;
+        if (bt >= 2) {
+            c->time_block = bt;
             c->tb_rows = btr;
             c->tb_zchunk = btz;
         } else {

@@ -120,7 +120,8 @@ struct fdtd_ctx {
     int4* ftiles = nullptr;         // fused frame tiles (0, x0, y0, z chunk)
     int nftiles = 0, ftile_cap = 0, fblocks = 0, fcz = 0, frows = 0;
     bfdtd::Frame ftile_rect{0, 0, 0, 0};
-    // steps per pass over the fields (time_block 2: the two-step kernel)
+    // steps per pass over the fields (time_block 2: the two-step kernel, 3:
+    // the three-step kernel, with pairs and single steps for the rest)
     int time_block = 1, tb_rows = 4, tb_zchunk = 0;
     bfdtd::SideStreams side{};     // the two-step kernel's boundary launches
     bool side_ok = false;
@@ -319,12 +320,17 @@ inline hipError_t launch_step(const fdtd_ctx* c, const Problem& q, long long n, 
                               c->timer);
 }
 
-// Pairs of steps go through the two-step kernel when it is selected, the
-// fused kernel is in use, the walls are not periodic, and neither the energy
-// record nor a plane record is wanted (those need every step's state).
+// Pairs of steps go through the two-step kernel when it (or the
+// three-step kernel) is selected, the fused kernel is in use, the walls are
+// not periodic, and neither the energy record nor a plane record is wanted
+// (those need every step's state); triples go through the three-step kernel
+// under the same conditions when it is selected.
 inline bool two_step_on(const fdtd_ctx* c) {
-    return c->time_block == 2 && c->kernel != FDTD_KERNEL_SPLIT && !c->p.periodic &&
-           !(c->mask & FDTD_DIAG_ENERGY) && !c->p.rec;
+    return (c->time_block == 2 || c->time_block == 3) && c->kernel != FDTD_KERNEL_SPLIT &&
+           !c->p.periodic && !(c->mask & FDTD_DIAG_ENERGY) && !c->p.rec;
+}
+inline bool three_step_on(const fdtd_ctx* c) {
+    return c->time_block == 3 && two_step_on(c);
 }
 
 // Steps n and n + 1 in one pass over the whole grid: the two-step kernel
@@ -382,6 +388,26 @@ inline void launch_pair(fdtd_ctx* c, long long n, bool trial = false) {
     c->count += (m0 != 0) + (m1 != 0);
     c->parity ^= 1;
     c->step += 2;
+}
+
+// Steps n .. n + 2 in one pass over the whole grid through the three-step
+// kernel (parity par to par ^ 1); trial as for launch_pair.
+inline void launch_triple(fdtd_ctx* c, long long n, bool trial = false) {
+    const int par = c->parity;
+    Problem q = c->p;
+    q.plane = c->plane;
+    const unsigned dm = trial ? 0u : c->mask & 7u;
+    const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
+    const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
+    const int m2 = (c->plane >= 0 && n + 2 >= c->wbegin) ? (int)dm : 0;
+    if (c->concurrent) ensure_side_streams(c);
+    check(launch_step3(q, n, par, c->tb_rows, c->tb_zchunk, m0, m1, m2, c->stream, c->timer,
+                       c->concurrent ? &c->side : nullptr),
+          "three-step launch");
+    if (trial) return;
+    c->count += (m0 != 0) + (m1 != 0) + (m2 != 0);
+    c->parity ^= 1;
+    c->step += 3;
 }
 
 }  // namespace bfdtd

@@ -152,6 +152,14 @@ hipError_t launch_step2(const Problem& p, long long n, int parity, int rows, int
                         const SideStreams* side);
 // Cells (times nz) of the interior-class launch: tiles with no wall or CPML
 long long step2_interior_cells(const Problem& p, int rows);
+// The three-step kernel (kernels_step3.hip): as launch_step2 with a third
+// step, from parity `parity` at step n to parity ^ 1 at step n + 3 (mask0..2:
+// plane accumulation of steps n .. n + 2), in the same four tile classes
+// (58-cell x segments). Not for the periodic test mode.
+hipError_t launch_step3(const Problem& p, long long n, int parity, int rows, int zchunk,
+                        int mask0, int mask1, int mask2, hipStream_t s, LaunchTimer* timer,
+                        const SideStreams* side);
+long long step3_interior_cells(const Problem& p, int rows);
 // The two-step kernel over many instances: work items (instance, segment,
 // row group, kb | ke << 16) per tile class (0 interior, 1 x boundary, 2 y
 // boundary, 3 corner; nz < 65536), and one pair of steps of every instance

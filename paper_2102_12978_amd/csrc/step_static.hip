@@ -101,7 +101,7 @@ extern "C" int fdtd_step_static(fdtd_ctx* c, int64_t nsteps) {
                  FDTD_ESTATE);
         }
         const bool energy = (c->mask & FDTD_DIAG_ENERGY) != 0;
-        const bool pairs = two_step_on(c);
+        const bool pairs = two_step_on(c), triples = three_step_on(c);
         int np = 0;
         double* part = nullptr;
         if (energy) {
@@ -116,6 +116,22 @@ extern "C" int fdtd_step_static(fdtd_ctx* c, int64_t nsteps) {
         }
         for (int64_t s = 0; s < nsteps;) {
             const long long n = c->step;
+            if (triples && nsteps - s >= 3) {
+                Problem q = c->p;
+                q.plane = c->plane;
+                const unsigned dm = c->mask & 7u;
+                const int m0 = (c->plane >= 0 && n >= c->wbegin) ? (int)dm : 0;
+                const int m1 = (c->plane >= 0 && n + 1 >= c->wbegin) ? (int)dm : 0;
+                const int m2 = (c->plane >= 0 && n + 2 >= c->wbegin) ? (int)dm : 0;
+                check(launch_step3(q, n, c->parity, c->tb_rows, c->tb_zchunk, m0, m1, m2,
+                                   c->stream, nullptr, nullptr),
+                      "three-step launch");
+                c->count += (m0 != 0) + (m1 != 0) + (m2 != 0);
+                c->parity ^= 1;
+                c->step += 3;
+                s += 3;
+                continue;
+            }
             if (pairs && nsteps - s >= 2) {
                 Problem q = c->p;
                 q.plane = c->plane;

@@ -39,10 +39,13 @@ def kernel_sha256_16(path=KERNEL_SRC):
 
 
 def source_of(kernel):
-    """Source file of a kernel (by the name the counters carry): the two-step
-    kernel, the one-step interior kernel, or the split frame kernels."""
+    """Source file of a kernel (by the name the counters carry): the two- or
+    three-step kernel, the one-step interior kernel, or the split frame
+    kernels."""
     if "step2" in kernel:
         return os.path.join(CSRC, "kernels_step2.hip")
+    if "step3" in kernel:
+        return os.path.join(CSRC, "kernels_step3.hip")
     if "split_" in kernel:
         return os.path.join(CSRC, "kernels_split.hip")
     return os.path.join(CSRC, "kernels_fused.hip")

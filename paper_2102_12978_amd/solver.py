@@ -274,8 +274,9 @@ class Solver:
         self._c(self._lib.fdtd_set_frame(self._ctx, int(kind), int(xalign), int(rows)))
 
     def set_time_block(self, steps, rows=4, zchunk=0):
-        """Steps per pass over the interior: 1, or 2 (the two-step kernel
-        with tiles of `rows` rows and z chunks of `zchunk` planes)."""
+        """Steps per pass over the fields: 1, 2 (the two-step kernel) or 3
+        (the three-step kernel), with tiles of `rows` rows and z chunks of
+        `zchunk` planes."""
         self._c(self._lib.fdtd_set_time_block(self._ctx, int(steps), int(rows), int(zchunk)))
 
     def set_concurrency(self, on=True):

@@ -3,7 +3,7 @@ fdtd_step through the C ABI: fields, CPML memories, plane sums and the
 energy must agree bit for bit, on two calls in a row on two grids, the
 second smaller (the shared static scratch keeps the first call's
 contents), with the energy diagnostic (its partial sums in the static
-scratch) and with the two-step kernel; steps past the time tables and a
+scratch) and with the two- and three-step kernels; steps past the time tables and a
 grid whose energy partials exceed the static scratch are refused without
 stepping."""
 import numpy as np
@@ -21,8 +21,8 @@ def _pair(w, time_block):
     out = []
     for _ in range(2):
         s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
-        if time_block == 2:
-            s.set_time_block(2, 2, 8)
+        if time_block > 1:
+            s.set_time_block(time_block, 2, 8)
         out.append(s)
     return out
 
@@ -34,11 +34,12 @@ def _same_state(a, b, npml):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), q
 
 
-@pytest.mark.parametrize("time_block", [1, 2])
+@pytest.mark.parametrize("time_block", [1, 2, 3])
 def test_static_step_equals_step_on_two_grids(time_block):
     """300x150 then the smaller 100x72 grid, each stepped through both entry
     points: energy diagnostic on (one step per launch, partials in the
-    static scratch), then off for 13 more steps (pairs with time_block 2)."""
+    static scratch), then off for 13 more steps (pairs with time_block 2,
+    triples and a single step with time_block 3)."""
     for w in (W.parity_mid(), W.parity_small()):
         ref, st = _pair(w, time_block)
         for s in (ref, st):
