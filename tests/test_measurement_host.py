@@ -131,29 +131,30 @@ def test_committed_profiles_run_committed_files_only():
         assert "_work" not in text and "/root/reference" not in text, n
 
 
-def test_step_traffic_records_are_tied_to_the_kernel_source_and_tile():
+@pytest.mark.parametrize("kind", ["step2", "step3"])
+def test_step_traffic_records_are_tied_to_the_kernel_source_and_tile(kind):
     import bench
     names = [n for n in os.listdir(os.path.join(ROOT, "profiles"))
-             if n.startswith("step2_pass_768x768x255_rows") and n.endswith("_traffic.json")]
+             if n.startswith(f"{kind}_pass_768x768x255_rows") and n.endswith("_traffic.json")]
     assert names
     for n in names:
         t = json.load(open(os.path.join(ROOT, "profiles", n)))
-        assert t["kernel"] == "step2_pass" and len(t["launches"]) == 4
+        assert t["kernel"] == f"{kind}_pass" and len(t["launches"]) == 4
         assert t["bytes_per_launch"] == t["read_bytes_per_launch"] + t["write_bytes_per_launch"]
         assert len(t["kernel_sha256_16"]) == 16
         rows, zc = t["tile"]["rows"], t["tile"]["zchunk"]
-        assert n == f"step2_pass_768x768x255_rows{rows}_z{zc}_traffic.json"
-        # every launch of the summary is the two-step kernel at that tile height
-        assert all(l["kernel"].startswith(f"step2_kernel<{rows},") for l in t["launches"])
+        assert n == f"{kind}_pass_768x768x255_rows{rows}_z{zc}_traffic.json"
+        # every launch of the summary is the pass kernel at that tile height
+        assert all(l["kernel"].startswith(f"{kind}_kernel<{rows},") for l in t["launches"])
         # the bench line takes this record for its own tile shape only, and
         # only while the kernel source is the one profiled
-        got = bench.measured_traffic("step2_pass", (rows, zc))
-        if t["kernel_sha256_16"] == bench.kernel_hash("step2_pass"):
+        got = bench.measured_traffic(f"{kind}_pass", (rows, zc))
+        if t["kernel_sha256_16"] == bench.kernel_hash(f"{kind}_pass"):
             assert got == t["bytes_per_launch"]
         else:
             assert got is None
-    assert bench.measured_traffic("step2_pass", (3, 7)) is None
-    assert bench.measured_traffic("step2_pass", None) is None
+    assert bench.measured_traffic(f"{kind}_pass", (3, 7)) is None
+    assert bench.measured_traffic(f"{kind}_pass", None) is None
 
 
 def test_bench_refuses_more_than_one_gpu():
