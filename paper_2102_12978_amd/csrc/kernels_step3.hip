@@ -150,10 +150,15 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
                (size_t)(long long)x0;
     };
     const unsigned lo4 = 4u * (unsigned)(xc - x0);
+    // Every row load is unconditional, as for the lanes: a row outside the
+    // grid reads the nearest row inside it. Its values feed only rows
+    // outside the grid (E there is zeroed after every E stage) and E_x,
+    // E_z held on the y = 0 wall, at every stage. (A load under a branch
+    // per row, as the two-step kernel has, here made the compiler wait for
+    // each such load and store it to scratch memory.)
     auto ld = [&](int c, int kk, int r) {
-        float v = 0.f;
-        if (row_ok(r)) v = *(gptr<const float>)(uniform3(fo + base(c, kk, r)) + lo4);
-        return v;
+        const int rc = YB ? min(max(j0 + r, 0), ny - 1) - j0 : r;
+        return *(gptr<const float>)(uniform3(fo + base(c, kk, rc)) + lo4);
     };
     auto st = [&](int c, int kk, int r, float v) {
         *(gptr<float>)(uniform3(fw + base(c, kk, r)) + lo4) = v;
@@ -167,44 +172,58 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
         ex_c = Coef3{cx_tab(p, T_EB)[x], cx_tab(p, T_EC)[x], cx_tab(p, T_EK)[x]};
         hx_c = Coef3{cx_tab(p, T_HB)[x], cx_tab(p, T_HC)[x], cx_tab(p, T_HK)[x]};
     }
-    // y slab index and coefficients of the formed rows -2 .. TY+2
+    // y slab index of the formed rows -2 .. TY+2 (uniform per row)
     constexpr int NR = YB ? TY + 6 : 1;
     int ysl_r[NR];
-    Coef3 eyc[NR], hyc[NR];
     if constexpr (YB) {
         ysl_r[0] = -1;
 #pragma unroll
-        for (int r = -2; r <= TY + 2; ++r) {
-            const int j = j0 + r;
-            ysl_r[O + r] = row_ok(r) ? slab_index(j, ny, npml) : -1;
-            eyc[O + r] = Coef3{0.f, 0.f, 1.f};
-            hyc[O + r] = Coef3{0.f, 0.f, 1.f};
-            if (ysl_r[O + r] >= 0) {
-                eyc[O + r] = Coef3{cy_tab(p, T_EB)[j], cy_tab(p, T_EC)[j], cy_tab(p, T_EK)[j]};
-                hyc[O + r] = Coef3{cy_tab(p, T_HB)[j], cy_tab(p, T_HC)[j], cy_tab(p, T_HK)[j]};
-            }
-        }
+        for (int r = -2; r <= TY + 2; ++r)
+            ysl_r[O + r] = row_ok(r) ? slab_index(j0 + r, ny, npml) : -1;
     }
     auto ysl = [&](int r) {
         if constexpr (YB) return ysl_r[O + r];
         return -1;
     };
-    const gptr<const float> po = G((const float*)p.pbase[par]);
+    // The y coefficients of those rows (b, c, 1/κ at E and at H positions:
+    // six per row) are copied into LDS once per tile and read where a stage
+    // uses them, rather than held in scalar registers for the whole tile
+    // (those tiles run short of them). Each wavefront reads only the rows it
+    // wrote.
+    extern __shared__ float2 amp_lds3[];
+    constexpr int NCF = YB ? WAVES * (TY + 5) * 6 : 0;   // floats of coefficients
+    float* const ycf = reinterpret_cast<float*>(amp_lds3);
+    auto ycf_at = [&](int r, int t) { return (w * (TY + 5) + r + 2) * 6 + t; };
+    if constexpr (YB) {
+        if (lane < (TY + 5) * 6) {
+            const int r = lane / 6 - 2, t = lane % 6;
+            const int j = min(max(j0 + r, 0), ny - 1);
+            const int tab = t < 3 ? T_EB + t : T_HB + (t - 3);
+            ycf[ycf_at(r, t)] = npml > 0 ? cy_tab(p, tab)[j] : 0.f;
+        }
+    }
+    // Without CPML (npml = 0) there are no memories: the memory loads below
+    // then read the fields instead (in bounds), and nothing uses the values.
+    const gptr<const float> po = npml > 0 ? G((const float*)p.pbase[par]) : fo;
     const gptr<float> pw = G(p.pbase[par ^ 1]);
     auto xq = [&](int kk, int r) { return ((size_t)kk * ny + (j0 + r)) * (2 * npml) + xsl; };
+    // the row a load reads: the nearest inside the grid (y-boundary tiles)
+    auto row_in = [&](int r) { return YB ? min(max(j0 + r, 0), ny - 1) - j0 : r; };
     auto yq = [&](int kk, int r) {
         return ((size_t)kk * (2 * npml) + ysl(r)) * p.pitch + xc;
     };
-    auto ldx = [&](int q, int kk, int r) {   // x-slab memory q (slab lanes only)
-        float v = 0.f;
-        if (row_ok(r) && xsl >= 0) v = po[psi_offset(p, q) + xq(kk, r)];
-        return v;
+    auto ldx = [&](int q, int kk, int r) {   // x-slab memory q (used on slab lanes only)
+        // unconditional: a lane off the slabs reads slab column 0 of the row
+        // (the nearest row inside the grid), and the stages use no memory
+        // off the slabs
+        const size_t i = ((size_t)kk * ny + (j0 + row_in(r))) * (2 * npml) + max(xsl, 0);
+        return po[psi_offset(p, q) + i];
     };
     auto stx = [&](int q, int kk, int r, float v) { pw[psi_offset(p, q) + xq(kk, r)] = v; };
-    auto ldy = [&](int q, int kk, int r) {   // y-slab memory q (slab rows only)
-        float v = 0.f;
-        if (ysl(r) >= 0) v = po[psi_offset(p, q) + yq(kk, r)];
-        return v;
+    auto ldy = [&](int q, int kk, int r) {   // y-slab memory q (used on slab rows only)
+        // unconditional, like the field rows: a row off the slabs reads slab
+        // row 0 of its plane, and the stages use no memory off the slabs
+        return po[psi_offset(p, q) + ((size_t)kk * (2 * npml) + max(ysl(r), 0)) * p.pitch + xc];
     };
     auto sty = [&](int q, int kk, int r, float v) { pw[psi_offset(p, q) + yq(kk, r)] = v; };
 
@@ -225,8 +244,7 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
     // from row -2 of its first wavefront; rows two stacked wavefronts share
     // are written by both with the same values, and a wavefront reads only
     // rows it wrote itself.
-    extern __shared__ float2 amp_lds3[];
-    auto lds_at = [&](int r, int c) { return ((w * TY + r + 2) * 6 + c) * 64 + lane; };
+    auto lds_at = [&](int r, int c) { return NCF / 2 + ((w * TY + r + 2) * 6 + c) * 64 + lane; };
     if (src) {
 #pragma unroll
         for (int r = -2; r <= TY + 2; ++r) {
@@ -281,7 +299,7 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
         }
         if constexpr (YB) {
             if (ysl(r) >= 0) {
-                const Coef3 cy = eyc[O + r];
+                const Coef3 cy{ycf[ycf_at(r, 0)], ycf[ycf_at(r, 1)], ycf[ycf_at(r, 2)]};
                 if (!hy0) pxy = cpml_mem(cy.b, pxy, cy.c, d_yhz);
                 const float b2 = cpml_mem(cy.b, pzy, cy.c, d_yhx);
                 if (!hy0 && !hold_x) pzy = b2;
@@ -305,7 +323,7 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
         }
         if constexpr (YB) {
             if (ysl(r) >= 0) {
-                const Coef3 cy = hyc[O + r];
+                const Coef3 cy{ycf[ycf_at(r, 3)], ycf[ycf_at(r, 4)], ycf[ycf_at(r, 5)]};
                 pxy = cpml_mem(cy.b, pxy, cy.c, d_yez);
                 pzy = cpml_mem(cy.b, pzy, cy.c, d_yex);
                 ty_ez = stretched(cy.k, d_yez, pxy);
@@ -658,6 +676,12 @@ step3_kernel(Problem p, long long n, int par, Launch3 L, int nblocks_padded, int
 constexpr unsigned amp_lds_bytes3(int ty) {
     return (unsigned)((WAVES * ty + 5) * 6 * 64 * sizeof(float2));
 }
+// LDS of the y CPML coefficients of a y-boundary or corner workgroup: six
+// per formed row of each wavefront (672 B at TY = 2), ahead of the
+// amplitudes.
+constexpr unsigned ycf_lds_bytes3(int ty) {
+    return (unsigned)(WAVES * (ty + 5) * 6 * sizeof(float));
+}
 
 // Segments and row groups whose tiles form only regular cells (an interval
 // each, possibly empty).
@@ -712,9 +736,9 @@ hipError_t launch_class3(const Problem& p, long long n, int parity, const Launch
     if (nt <= 0) return hipSuccess;
     const int nbp = (nt + 7) / 8 * 8;
     if (timer) timer->mark_on(name, s);
-    hipLaunchKernelGGL((step3_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES),
-                       p.colmap ? amp_lds_bytes3(TY) : 0, s, p, n, parity, L, nbp, mask0, mask1,
-                       mask2);
+    const unsigned lds = (p.colmap ? amp_lds_bytes3(TY) : 0u) + (YB ? ycf_lds_bytes3(TY) : 0u);
+    hipLaunchKernelGGL((step3_kernel<TY, XB, YB>), dim3(nbp), dim3(64 * WAVES), lds, s, p, n,
+                       parity, L, nbp, mask0, mask1, mask2);
     hipError_t e = hipGetLastError();
     if (timer) timer->mark_on(nullptr, s);
     return e;
