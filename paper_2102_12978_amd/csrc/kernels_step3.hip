@@ -29,7 +29,11 @@
 // the z phases e^{iβz} and time factors with scalar loads (the phases of
 // planes q-1 .. q-3 carried in registers) and the antenna amplitudes from
 // LDS (staged once per tile), so that no stage waits for a vector load and
-// with it for the plane's stores in flight.
+// with it for the plane's stores in flight. Boundary tiles load every row
+// and CPML memory unconditionally (rows outside the grid read the nearest
+// row inside it; lanes and rows off the slabs read slab column or row 0)
+// and keep their y coefficients in LDS: a load under a branch there made
+// the compiler wait for it and move it to scratch memory.
 // A workgroup stacks four wavefronts in y that start every plane together
 // (one barrier per plane): a row group of 4 TY rows.
 //
@@ -151,14 +155,12 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
     };
     const unsigned lo4 = 4u * (unsigned)(xc - x0);
     // Every row load is unconditional, as for the lanes: a row outside the
-    // grid reads the nearest row inside it. Its values feed only rows
-    // outside the grid (E there is zeroed after every E stage) and E_x,
-    // E_z held on the y = 0 wall, at every stage. (A load under a branch
-    // per row, as the two-step kernel has, here made the compiler wait for
-    // each such load and store it to scratch memory.)
+    // grid reads the nearest row inside it (row_in). Its values feed only
+    // rows outside the grid (E there is zeroed after every E stage) and E_x,
+    // E_z held on the y = 0 wall, at every stage.
+    auto row_in = [&](int r) { return YB ? min(max(j0 + r, 0), ny - 1) - j0 : r; };
     auto ld = [&](int c, int kk, int r) {
-        const int rc = YB ? min(max(j0 + r, 0), ny - 1) - j0 : r;
-        return *(gptr<const float>)(uniform3(fo + base(c, kk, rc)) + lo4);
+        return *(gptr<const float>)(uniform3(fo + base(c, kk, row_in(r))) + lo4);
     };
     auto st = [&](int c, int kk, int r, float v) {
         *(gptr<float>)(uniform3(fw + base(c, kk, r)) + lo4) = v;
@@ -197,9 +199,8 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
     if constexpr (YB) {
         if (lane < (TY + 5) * 6) {
             const int r = lane / 6 - 2, t = lane % 6;
-            const int j = min(max(j0 + r, 0), ny - 1);
             const int tab = t < 3 ? T_EB + t : T_HB + (t - 3);
-            ycf[ycf_at(r, t)] = npml > 0 ? cy_tab(p, tab)[j] : 0.f;
+            ycf[ycf_at(r, t)] = npml > 0 ? cy_tab(p, tab)[j0 + row_in(r)] : 0.f;
         }
     }
     // Without CPML (npml = 0) there are no memories: the memory loads below
@@ -207,8 +208,6 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
     const gptr<const float> po = npml > 0 ? G((const float*)p.pbase[par]) : fo;
     const gptr<float> pw = G(p.pbase[par ^ 1]);
     auto xq = [&](int kk, int r) { return ((size_t)kk * ny + (j0 + r)) * (2 * npml) + xsl; };
-    // the row a load reads: the nearest inside the grid (y-boundary tiles)
-    auto row_in = [&](int r) { return YB ? min(max(j0 + r, 0), ny - 1) - j0 : r; };
     auto yq = [&](int kk, int r) {
         return ((size_t)kk * (2 * npml) + ysl(r)) * p.pitch + xc;
     };
