@@ -147,10 +147,14 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
                (size_t)(long long)x0;
     };
     const unsigned lo4 = 4u * (unsigned)(xc - x0);
+    // Every row load is unconditional, as for the lanes: a row outside the
+    // grid reads the nearest row inside it (row_in). Its values feed only
+    // rows outside the grid (E there is zeroed after every E update) and
+    // E_x, E_z held on the y = 0 wall. A load under a per-row branch can
+    // make the compiler wait for it before the next one issues.
+    auto row_in = [&](int r) { return YB ? min(max(j0 + r, 0), ny - 1) - j0 : r; };
     auto ld = [&](int c, int kk, int r) {
-        float v = 0.f;
-        if (row_ok(r)) v = *(gptr<const float>)(uniform(fo + base(c, kk, r)) + lo4);
-        return v;
+        return *(gptr<const float>)(uniform(fo + base(c, kk, row_in(r))) + lo4);
     };
     // plain stores: a tile stores 60 cells of a row, so lines at tile edges
     // are written by two tiles and merge in L2
@@ -187,22 +191,24 @@ __device__ __forceinline__ void step2_tile(const Problem& p, long long n, int pa
         if constexpr (YB) return ysl_r[O + r];
         return -1;
     };
-    const gptr<const float> po = G((const float*)p.pbase[par]);
+    // Without CPML (npml = 0) there are no memories: the memory loads below
+    // then read the fields instead (in bounds), and nothing uses the values.
+    const gptr<const float> po = npml > 0 ? G((const float*)p.pbase[par]) : fo;
     const gptr<float> pw = G(p.pbase[par ^ 1]);
     auto xq = [&](int kk, int r) { return ((size_t)kk * ny + (j0 + r)) * (2 * npml) + xsl; };
     auto yq = [&](int kk, int r) {
         return ((size_t)kk * (2 * npml) + ysl(r)) * p.pitch + xc;
     };
-    auto ldx = [&](int q, int kk, int r) {   // x-slab memory q (slab lanes only)
-        float v = 0.f;
-        if (row_ok(r) && xsl >= 0) v = po[psi_offset(p, q) + xq(kk, r)];
-        return v;
+    // CPML memory loads are unconditional too: a lane or row off the slabs
+    // reads slab column or row 0 (of the nearest row inside the grid), and
+    // no update uses a memory off the slabs.
+    auto ldx = [&](int q, int kk, int r) {   // x-slab memory q (used on slab lanes only)
+        const size_t i = ((size_t)kk * ny + (j0 + row_in(r))) * (2 * npml) + max(xsl, 0);
+        return po[psi_offset(p, q) + i];
     };
     auto stx = [&](int q, int kk, int r, float v) { pw[psi_offset(p, q) + xq(kk, r)] = v; };
-    auto ldy = [&](int q, int kk, int r) {   // y-slab memory q (slab rows only)
-        float v = 0.f;
-        if (ysl(r) >= 0) v = po[psi_offset(p, q) + yq(kk, r)];
-        return v;
+    auto ldy = [&](int q, int kk, int r) {   // y-slab memory q (used on slab rows only)
+        return po[psi_offset(p, q) + ((size_t)kk * (2 * npml) + max(ysl(r), 0)) * p.pitch + xc];
     };
     auto sty = [&](int q, int kk, int r, float v) { pw[psi_offset(p, q) + yq(kk, r)] = v; };
 
