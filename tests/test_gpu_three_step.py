@@ -285,3 +285,24 @@ def test_gradient_with_three_step_forward():
     (i1, a1, p1), (i2, a2, p2) = out
     assert np.array_equal(i1, i2)
     assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+
+
+def test_no_buffer_and_bad_arguments():
+    """Three-step passes allocate nothing (device_bytes unchanged after
+    selecting them and stepping), and tile shapes the kernel does not have
+    are refused with FDTD_EINVAL, leaving the selection as it was."""
+    w = W.parity_mid()
+    s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED)
+    s.step(2)
+    b0 = s.info().device_bytes
+    s.set_time_block(3, 2, 8)
+    s.step(6)
+    inf = s.info()
+    assert inf.device_bytes == b0 and inf.time_block == 3 and inf.step == 8
+    for args in ((3, 8, 0), (3, 3, 0), (3, 2, -1), (3, 2, 10**6)):
+        with pytest.raises(L.FdtdError) as e:
+            s.set_time_block(*args)
+        assert e.value.code == L.EINVAL
+    inf = s.info()
+    assert (inf.time_block, inf.tb_rows, inf.tb_zchunk) == (3, 2, 8)
+    s.close()
