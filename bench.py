@@ -266,12 +266,15 @@ def shard_measure(torch, stream, parts, steps=1000, warmup=20, reps=5):
     it = s.info()
     cells = nx * ny * nz
     s.close()
-    # what a two-step pass would need from its ring neighbours (derived from
-    # the planes a z chunk reads beyond its ends, not measured): below, all
-    # six components of the plane under the slab and H_x, H_y of the one
-    # under that; above, all six of the plane over the slab and all but E_z
-    # of the one over that
+    # what a pass would need from its ring neighbours, in component-planes
+    # (derived from the planes a z chunk reads beyond its ends, not
+    # measured): one step, H_x, H_y of the plane under the slab and E_x,
+    # E_y of the one over it; a two-step pass, all six components of the
+    # plane under the slab and H_x, H_y of the one under that, and all six
+    # of the plane over it and all but E_z of the next; a three-step pass,
+    # one whole plane more on each side
     plane_bytes = nx * ny * 4
+    below, above = {1: (2, 2), 2: (8, 11), 3: (14, 17)}[it.time_block]
     return {
         "workload": f"768x768x{nz}: one of {parts} z-slabs of the 768x768x255 grid, z periodic "
                     "over the slab in place of the neighbour exchange",
@@ -281,8 +284,8 @@ def shard_measure(torch, stream, parts, steps=1000, warmup=20, reps=5):
         "steps_per_pass": it.time_block,
         "tile_rows": it.tb_rows if it.time_block >= 2 else it.tile_rows,
         "tile_zchunk": it.tb_zchunk if it.time_block >= 2 else it.tile_zchunk,
-        "halo_bytes_per_pass_from_below": 8 * plane_bytes,
-        "halo_bytes_per_pass_from_above": 11 * plane_bytes,
+        "halo_bytes_per_pass_from_below": below * plane_bytes,
+        "halo_bytes_per_pass_from_above": above * plane_bytes,
     }
 
 
