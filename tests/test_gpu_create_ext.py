@@ -1,6 +1,6 @@
 """Fields in caller-owned device memory (fdtd_create_ext): two torch tensors
 hold the two field parities. A run on them equals a run on library-owned
-buffers bit for bit (one- and two-step passes, antenna on, CPML memories
+buffers bit for bit (one-, two- and three-step passes, antenna on, CPML memories
 included); the current-state buffer read through torch equals fdtd_get_state;
 the library zeroes the buffers at create and leaves them alive at destroy;
 buffers the kernels could not use are rejected on the host."""
@@ -74,6 +74,12 @@ def test_external_fields_bit_identical():
     assert s.info().time_block == 2
     _assert_identical(s, r, "two-step pairs, 22 steps")
     _check_view(s, bufs, pitch, "two-step")
+    for x in (s, r):
+        x.set_time_block(3, 2, 8)
+        x.step(10)
+    assert s.info().time_block == 3
+    _assert_identical(s, r, "three-step passes, 32 steps")
+    _check_view(s, bufs, pitch, "three-step")
     assert np.array_equal(s.fluence(L.DIAG_EY2), r.fluence(L.DIAG_EY2))
     # the two field buffers are not counted as the library's memory
     assert s.info().device_bytes < r.info().device_bytes
