@@ -67,14 +67,15 @@ def test_large_grid_sampled_columns():
     assert rel <= 1e-5 and worst <= 1e-5
 
 
-@pytest.mark.parametrize("time_block", [1, 2])
+@pytest.mark.parametrize("time_block", [1, 2, 3])
 def test_component_beyond_4_gib(time_block):
     """A grid whose field components exceed 4 GiB (2048×1024×536, 1.12 G
     cells, 54 GB of fields): planes past 512 lie beyond 32-bit byte offsets,
-    so the fused kernel takes 64-bit plane bases (the two-step kernel always
-    does). Random fields in windows around sampled columns (zero elsewhere),
-    antenna on, three steps (one pair and a single step with time_block 2);
-    whole columns (every plane) against the windowed FP64 oracle."""
+    so the fused kernel takes 64-bit plane bases (the two- and three-step
+    kernels always do). Random fields in windows around sampled columns
+    (zero elsewhere), antenna on, three steps (one pair and a single step
+    with time_block 2, one pass with time_block 3); whole columns (every
+    plane) against the windowed FP64 oracle."""
     w = W.Workload("big_2048x1024x536_theta20_m1", 2048, 1024, 540, 24.0, 20.0, 1, 400.0, 2.0,
                    16, 3)
     steps = 3
@@ -82,14 +83,17 @@ def test_component_beyond_4_gib(time_block):
     assert g.nz * g.ny * 2048 * 4 > (1 << 32)
     # antenna ring, interior, frame, and the two-step kernel's tile boundary
     # (x = 632), rectangle edges (x 32 / 2015, y 18 / 1005) and the last,
-    # left-shifted tile (x 1956)
+    # left-shifted tile (x 1956); the three-step kernel's segment edges
+    # (x = 38 + 58 k: 618, and 2010, where its last segment starts)
     cols = [(1024 - 399, 512), (1024 + 399, 512), (1024, 512 + 399), (700, 300), (64, 700),
             (2040, 1010), (1500, 16), (1024, 512), (632, 400), (32, 600), (2015, 777),
-            (1956, 1005), (1300, 18)]
+            (1956, 1005), (1300, 18), (618, 450), (2010, 820)]
     h = steps + 2
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=16)
     if time_block == 2:
         s.set_time_block(2, 4, 32)
+    if time_block == 3:
+        s.set_time_block(3, 2, 32)
     ant = P.build_antenna(g, cases.oracle_injector(w))
     rng = np.random.default_rng(11)
     fields = {}
