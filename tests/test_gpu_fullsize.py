@@ -1,16 +1,19 @@
 """Parity at the benchmark's full size: 768×768×255, Δx = λ/24, θ = 20°,
-order 2, annulus 320Δx, 16-cell CPML, in the benchmark's launch shape (fused
-interior kernel, 4 rows per wavefront, z chunks of 16, split frame).
+order 2, annulus 320Δx, 16-cell CPML, in the launch shape the benchmark
+times (one three-step pass: 2 rows per wavefront, z chunks of 32, the four
+tile classes concurrent) and in the one-step shape (fused interior kernel,
+4 rows per wavefront, z chunks of 16, split frame).
 
 From a seeded random state (fields U(-1,1), random CPML memories, E held at
 the walls zeroed) and with the antenna on, three steps run on the GPU; then
 whole z-columns at sampled (x, y) positions are compared with the FP64
 oracle, each computed exactly from a small window of the same initial state
 (tests/window.py). The columns sit on interior segment and row-group
-boundaries (x0 - 1 / x0, last / first row of a group), on the interior's
-edge and the frame next to it, in the CPML slabs and corners, and on the
-antenna ring; every z plane of each column is compared, so every z-chunk
-boundary is crossed."""
+boundaries of both shapes (x0 - 1 / x0, last / first row of a group; the
+three-step segments start at x = 36 + 58 k), on the interior's edge and
+the frame or boundary tiles next to it, in the CPML slabs and corners, and
+on the antenna ring; every z plane of each column is compared, so every
+z-chunk boundary is crossed."""
 import numpy as np
 import pytest
 
@@ -26,13 +29,21 @@ pytestmark = pytest.mark.gpu
 
 COLUMNS = [(95, 100), (96, 101), (32, 17), (31, 16), (735, 748), (736, 749), (400, 20),
            (400, 21), (8, 400), (760, 400), (400, 760), (5, 5), (762, 762), (704, 384),
-           (384, 64), (610, 610), (159, 383), (160, 384)]
+           (384, 64), (610, 610), (159, 383), (160, 384),
+           # three-step shape: x-boundary / interior segment edges (36, 732),
+           # an interior segment edge (94), the first and last interior rows
+           # of the row groups at 2 rows per wavefront (24, 743)
+           (35, 300), (36, 301), (93, 200), (94, 201), (731, 500), (732, 501), (400, 23),
+           (401, 24), (402, 743), (403, 744)]
 
 
-def test_large_grid_sampled_columns():
+@pytest.mark.parametrize("shape", ["three-step", "one-step"])
+def test_large_grid_sampled_columns(shape):
     w = W.grid768()
     steps = 3
     s = GC.gpu_solver(w, kernel=L.KERNEL_FUSED, rows=4, zchunk=16)
+    if shape == "three-step":
+        s.set_time_block(3, 2, 32)
     g = cases.oracle_grid(w)
     ant = P.build_antenna(g, cases.oracle_injector(w))
     rng = np.random.default_rng(7)
@@ -48,7 +59,7 @@ def test_large_grid_sampled_columns():
         a = rng.uniform(-1.0, 1.0, size=s.state_shape(q)).astype(np.float32)
         s.set_state(q, a)
         slabs[name] = a
-    print(f"  random state set; {steps} steps in the benchmark launch shape", flush=True)
+    print(f"  random state set; {steps} steps, {shape} launch shape", flush=True)
     s.step(steps)
     got = {c: s.get_state(q) for q, c in enumerate(GC.COMPS)}
     s.close()
