@@ -17,9 +17,9 @@
 //      and 61-63 are halo and the wavefront stores lanes 3..60 (58 cells).
 //   y: E^{n+1} on rows -2 .. TY+2, H^{n+3/2} on -2 .. TY+1, E^{n+2} on
 //      -1 .. TY+1, H^{n+5/2} on -1 .. TY, E^{n+3} on 0 .. TY and H^{n+7/2}
-//      on the TY stored rows. Every component of a stage is formed on all of
-//      its rows (the two-step kernel prunes some; here the registers go to
-//      the third stage).
+//      on the TY stored rows. E_y is not formed on the last row of an E
+//      stage, nor H_y on the first row of the first two H stages: nothing
+//      reads them there (E_y and H_y have no y neighbour in the curls).
 //   z: at plane q the pipeline forms E^{n+1}(q), H^{n+3/2}(q-1),
 //      E^{n+2}(q-1), H^{n+5/2}(q-2), E^{n+3}(q-2) and H^{n+7/2}(q-3), keeping
 //      one plane of each in registers; a chunk [kb, ke) reads planes
@@ -285,13 +285,13 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
     // old step and receive the new ones.
     auto e_upd = [&](int r, float& vx, float& vy, float& vz, float d_yhz, float d_zhy,
                      float d_zhx, float d_xhz, float d_xhy, float d_yhx, float& pyx, float& pzx,
-                     float& pxy, float& pzy) {
+                     float& pxy, float& pzy, bool do_y) {
         const bool hy0 = hold_y(r);
         float tx_hz = d_xhz, tx_hy = d_xhy, ty_hz = d_yhz, ty_hx = d_yhx;
         if constexpr (XB) {
             const float a = cpml_mem(ex_c.b, pyx, ex_c.c, d_xhz);
             const float b2 = cpml_mem(ex_c.b, pzx, ex_c.c, d_xhy);
-            if (!hold_x) pyx = a;
+            if (do_y && !hold_x) pyx = a;
             if (!hold_x && !hy0) pzx = b2;
             tx_hz = stretched(ex_c.k, d_xhz, pyx);
             tx_hy = stretched(ex_c.k, d_xhy, pzx);
@@ -307,15 +307,15 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
             }
         }
         if (!hy0) vx += curl_pair(p.sy, ty_hz, p.sz, d_zhy);
-        if (!hold_x) vy += curl_pair(p.sz, d_zhx, p.sx, tx_hz);
+        if (do_y && !hold_x) vy += curl_pair(p.sz, d_zhx, p.sx, tx_hz);
         if (!hold_x && !hy0) vz += curl_pair(p.sx, tx_hy, p.sy, ty_hx);
     };
     auto h_upd = [&](int r, float& vx, float& vy, float& vz, float d_yez, float d_zey,
                      float d_zex, float d_xez, float d_xey, float d_yex, float& pyx, float& pzx,
-                     float& pxy, float& pzy) {
+                     float& pxy, float& pzy, bool do_y) {
         float tx_ez = d_xez, tx_ey = d_xey, ty_ez = d_yez, ty_ex = d_yex;
         if constexpr (XB) {
-            pyx = cpml_mem(hx_c.b, pyx, hx_c.c, d_xez);
+            if (do_y) pyx = cpml_mem(hx_c.b, pyx, hx_c.c, d_xez);
             pzx = cpml_mem(hx_c.b, pzx, hx_c.c, d_xey);
             tx_ez = stretched(hx_c.k, d_xez, pyx);
             tx_ey = stretched(hx_c.k, d_xey, pzx);
@@ -330,15 +330,16 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
             }
         }
         vx -= curl_pair(p.sy, ty_ez, p.sz, d_zey);
-        vy -= curl_pair(p.sz, d_zex, p.sx, tx_ez);
+        if (do_y) vy -= curl_pair(p.sz, d_zex, p.sx, tx_ez);
         vz -= curl_pair(p.sx, tx_ey, p.sy, ty_ex);
     };
     // E beyond the last cell of the grid is zero (the PEC wall)
     auto zero_out = [&](int r, float& vx, float& vy, float& vz) {
         if ((XB && !inb) || (YB && !row_ok(r))) vx = vy = vz = 0.f;
     };
-    // One E stage in place on rows [ra, rb]: E from H (plane k), Hp (plane
-    // k - 1) and the CPML memories of those rows, plus the source.
+    // One E stage in place on rows [ra, rb] (E_y on [ra, rb - 1]): E from H
+    // (plane k), Hp (plane k - 1) and the CPML memories of those rows, plus
+    // the source.
     auto e_stage = [&](float* vx, float* vy, float* vz, const float* hx, const float* hy,
                        const float* hz, const float* px, const float* py, float* myx,
                        float* mzx, float* mxy, float* mzy, int ra, int rb, float2 pt0,
@@ -350,22 +351,24 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
             const float hz_im = lane_below(hz[i]);
             const float hy_im = lane_below(hy[i]);
             float dm = 0.f;
+            const bool do_y = r < rb;
             e_upd(r, vx[i], vy[i], vz[i], hz[i] - hz[i - 1], hy[i] - py[i], hx[i] - px[i],
                   hz[i] - hz_im, hy[i] - hy_im, hx[i] - hx[i - 1], XB ? myx[i] : dm,
-                  XB ? mzx[i] : dm, YB ? mxy[i] : dm, YB ? mzy[i] : dm);
+                  XB ? mzx[i] : dm, YB ? mxy[i] : dm, YB ? mzy[i] : dm, do_y);
             if (slot[i] >= 0) {
                 vx[i] += cmul_re(amp_lds3[lds_at(r, EX)], pt0);
                 vz[i] += cmul_re(amp_lds3[lds_at(r, EZ)], pt1);
-                vy[i] += cmul_re(amp_lds3[lds_at(r, EY)], pt0);
+                if (do_y) vy[i] += cmul_re(amp_lds3[lds_at(r, EY)], pt0);
             }
             zero_out(r, vx[i], vy[i], vz[i]);
         }
     };
-    // One H stage in place on rows [ra, rb]: H from E (plane k), Eu (plane
-    // k + 1) and the CPML memories of those rows, plus the source.
+    // One H stage in place on rows [ra, rb] (H_y on [ray, rb]): H from E
+    // (plane k), Eu (plane k + 1) and the CPML memories of those rows, plus
+    // the source.
     auto h_stage = [&](float* vx, float* vy, float* vz, const float* ex, const float* ey,
                        const float* ez, const float* ux, const float* uy, float* myx,
-                       float* mzx, float* mxy, float* mzy, int ra, int rb, float2 qt0,
+                       float* mzx, float* mxy, float* mzy, int ra, int rb, int ray, float2 qt0,
                        float2 qt1) {
 #pragma unroll
         for (int r = -2; r <= TY + 2; ++r) {
@@ -374,12 +377,13 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
             const float ey_ip = lane_above(ey[i]);
             const float ez_ip = lane_above(ez[i]);
             float dm = 0.f;
+            const bool do_y = r >= ray;
             h_upd(r, vx[i], vy[i], vz[i], ez[i + 1] - ez[i], uy[i] - ey[i], ux[i] - ex[i],
                   ez_ip - ez[i], ey_ip - ey[i], ex[i + 1] - ex[i], XB ? myx[i] : dm,
-                  XB ? mzx[i] : dm, YB ? mxy[i] : dm, YB ? mzy[i] : dm);
+                  XB ? mzx[i] : dm, YB ? mxy[i] : dm, YB ? mzy[i] : dm, do_y);
             if (slot[i] >= 0) {
                 vx[i] += cmul_re(amp_lds3[lds_at(r, HX)], qt1);
-                vy[i] += cmul_re(amp_lds3[lds_at(r, HY)], qt1);
+                if (do_y) vy[i] += cmul_re(amp_lds3[lds_at(r, HY)], qt1);
                 vz[i] += cmul_re(amp_lds3[lds_at(r, HZ)], qt0);
             }
         }
@@ -479,8 +483,8 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
             gz[i] = hpz[i];
         }
         phase(za0, za1, tH[0], pt0, pt1);
-        h_stage(gx, gy, gz, e1x, e1y, e1z, ex, ey, ph_yx, ph_zx, ph_xy, ph_zy, -2, TY + 1, pt0,
-                pt1);
+        h_stage(gx, gy, gz, e1x, e1y, e1z, ex, ey, ph_yx, ph_zx, ph_xy, ph_zy, -2, TY + 1, -1,
+                pt0, pt1);
 
         // ---- E^{n+2}(q-1), rows -1 .. TY+1 ---------------------------------
         float fx[R], fy[R], fz[R];
@@ -508,7 +512,8 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
             uz[i] = h1z[i];
         }
         phase(zb0, zb1, tH[1], pt0, pt1);
-        h_stage(ux, uy, uz, e2x, e2y, e2z, fx, fy, qh_yx, qh_zx, qh_xy, qh_zy, -1, TY, pt0, pt1);
+        h_stage(ux, uy, uz, e2x, e2y, e2z, fx, fy, qh_yx, qh_zx, qh_xy, qh_zy, -1, TY, 0, pt0,
+                pt1);
 
         // ---- E^{n+3}(q-2), rows 0 .. TY --------------------------------------
         float vx[R], vy[R], vz[R];
@@ -557,7 +562,7 @@ __device__ __forceinline__ void step3_tile(const Problem& p, long long n, int pa
                 wz[i] = h2z[i];
             }
             phase(zc0, zc1, tH[2], pt0, pt1);
-            h_stage(wx, wy, wz, e3x, e3y, e3z, vx, vy, rh_yx, rh_zx, rh_xy, rh_zy, 0, TY - 1,
+            h_stage(wx, wy, wz, e3x, e3y, e3z, vx, vy, rh_yx, rh_zx, rh_xy, rh_zy, 0, TY - 1, 0,
                     pt0, pt1);
             if (own) {
 #pragma unroll
